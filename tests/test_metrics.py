@@ -1,0 +1,40 @@
+"""Host-side truth matching: ghost threshold (70 %), reconstructibility (>= 3 planes)."""
+import numpy as np
+
+from paper_2412_05041_amd import metrics
+
+
+def test_ghost_threshold_is_seventy_percent():
+    # cluster truths: 10 hits; track A has 7 from MC 1, track B 6 from MC 2
+    truth = np.array([1] * 7 + [5] * 3 + [2] * 6 + [-1] * 4)
+    off = np.array([0, 10, 20])
+    hits = np.arange(20)
+    mc, ghost = metrics.label_tracks(off, hits, truth)
+    assert ghost.tolist() == [False, True]
+    assert mc.tolist() == [1, -1]
+
+
+def test_noise_never_wins_cluster_truth():
+    pix_clu = np.array([0, 0, 0, 1, 1, 2])
+    pix_mc = np.array([-1, -1, 4, 3, 2, -1])
+    t = metrics.cluster_truth(pix_clu, pix_mc, 3)
+    assert t.tolist() == [4, 2, -1]  # noise majority loses; tie -> lower id; pure noise -> -1
+
+
+class _B:
+    pass
+
+
+def test_reconstructible_needs_three_planes():
+    b = _B()
+    b.n_events = 1
+    b.trk_off = np.array([0, 2])
+    # MC 0 on planes 0,1,2 ; MC 1 on planes 0,1 only
+    clu_off = np.zeros(27, np.int64)
+    for p in range(26):
+        clu_off[p + 1] = clu_off[p] + (2 if p < 2 else (1 if p == 2 else 0))
+    pix_clu = np.arange(5)
+    b.pix_mc = np.array([0, 1, 0, 1, 0])
+    r = metrics.eff_ghost(b, pix_clu, clu_off, np.array([0, 1]), np.array([0, 3]), np.array([0, 2, 4]))
+    assert r["n_reconstructible"] == 1
+    assert r["efficiency"] == 1.0 and r["ghost_rate"] == 0.0
