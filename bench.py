@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""VELO hot-path benchmark on one MI355X.
+
+Workload (the nominal-occupancy configuration): 1000 synthetic events, Poisson(5)
+primary vertices x Poisson(40) tracks, 1 mrad scattering per plane, calibrated
+noise giving ~3k clusters per event (seed 1002).  One step = the whole path
+(clustering + staging, track finding, acceptance, CSR output, fit) over the
+batch, inputs resident in HBM, launched as one replayed HIP graph.
+
+Prints ONE JSON line: events/s, the dominant kernel's HBM roofline fraction
+(algorithmic bytes / its HIP-event-timed duration), efficiency / ghost rate of
+the output, and the oracle timed on the host cores over a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode plain|learned]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "VELO events/s at nominal occupancy (1 GPU), eff/ghost rate; % HBM roofline"
+
+
+def _oracle_chunk(args):
+    """CPU baseline worker: the oracle (cluster + find + FP64 fit) on an event slice."""
+    import numpy as np  # noqa: F401
+    import oracle
+    pix_off, pix_id, plane_z, cuts = args
+    c = oracle.cluster(pix_off, pix_id)
+    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], plane_z, cuts)
+    oracle.fit(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], plane_z, cuts["sigma"])
+    return int(pix_off.size - 1) // 26
+
+
+def cpu_baseline(batch, cuts, passes):
+    import multiprocessing as mp
+
+    import oracle
+    oracle.build()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    chunks = []
+    step = max(1, batch.n_events // (cores * 4))
+    for e0 in range(0, batch.n_events, step):
+        s = batch.event_slice(e0, min(batch.n_events, e0 + step))
+        chunks.append((s.pix_off, s.pix_id, batch.plane_z, cuts))
+    ctx = mp.get_context("fork")  # no GPU has been touched yet in this process
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_chunk, chunks[:cores])  # warm the workers
+        t0 = time.perf_counter()
+        n = 0
+        for _ in range(passes):
+            n += sum(pool.map(_oracle_chunk, chunks))
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="events/s", cores=cores, kind="oracle",
+                sample=f"all {batch.n_events} events of the benchmark batch x {passes} passes, "
+                       f"event-parallel over {cores} worker processes; {dt:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", choices=["plain", "learned"], default="plain")
+    ap.add_argument("--workload", default="nominal")
+    ap.add_argument("--cpu-passes", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(events would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    from paper_2412_05041_amd import gen, metrics
+
+    cfg = os.path.join(ROOT, "paper_2412_05041_amd", "configs")
+    w = gen.WORKLOADS[args.workload]
+    cuts = json.load(open(os.path.join(cfg, "cuts_ms.json" if w.ms_sigma > 0 else "cuts_default.json")))
+    batch = gen.generate(w)
+    E = batch.n_events
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, cuts, args.cpu_passes)
+
+    import torch
+
+    from paper_2412_05041_amd import velo
+
+    if args.mode == "learned":
+        from paper_2412_05041_amd import learned
+        master, norm = learned.load_default_weights()
+        cuts = dict(cuts, mode=1, logit_band=learned.DEFAULT_BAND)
+    v = velo.Velo(batch.plane_z, cuts, device=0)
+    if args.mode == "learned":
+        v.mlp_set_weights(master, norm)
+    v.reserve(E, batch.n_pix, batch.n_pix)
+    off, ids = velo.to_device(batch)
+    if not args.no_autotune:
+        c = v.cluster(off, ids, with_npix=False)
+        v.autotune(c["clu_off"], c["clu_x"], c["clu_y"], reps=2)
+        del c
+    bufs = v.pipeline_buffers(E, batch.n_pix)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        v.pipeline(off, ids, bufs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v.pipeline(off, ids, bufs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * E / dt
+    st = v.read_status(bufs["status"])
+    if st[0] != 0:
+        print(f"status error: {st[:8]}", file=sys.stderr)
+        sys.exit(1)
+
+    # outputs, truth matching
+    n_clu = int(st[1])
+    T = int(st[2])
+    H = int(st[3])
+    clu_off = bufs["clu_off"].cpu().numpy()
+    m = metrics.eff_ghost(batch, bufs["pix_clu"][:batch.n_pix].cpu().numpy(), clu_off,
+                          bufs["trk_off"].cpu().numpy(), bufs["trk_hit_off"][:T + 1].cpu().numpy(),
+                          bufs["trk_hit"][:H].cpu().numpy())
+
+    # per-stage durations (HIP events on the launch stream, eager launches)
+    v.set_timing(True)
+    acc = None
+    for _ in range(args.steps):
+        v.pipeline(off, ids, bufs)
+        t = v.last_timing()
+        acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
+    v.set_timing(False)
+    stages = {k: acc[k] / args.steps for k in acc}
+    dom = max(("cluster", "find_lds", "find_large", "output_fit"), key=lambda k: stages[k])
+    # algorithmic bytes per launch (minimum traffic the stage must move)
+    n_pix = batch.n_pix
+    alg = {
+        "cluster": 8 * n_pix + 8 * n_clu + 14 * n_clu,    # ids in, labels out, centroids + staging out
+        "find_lds": 8 * n_clu + 4 * H + 8 * T,            # hit coordinates in, track hit lists out
+        "find_large": 8 * n_clu + 4 * H + 8 * T,
+        "output_fit": 12 * H + 40 * T,                    # gather hits, write CSR + 8-float state
+    }
+    achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
+    path_bytes = 8 * n_pix + 8 * n_clu + 4 * H + 36 * T  # fused minimum of the whole path
+    th, tl = v.get_launch()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {E} events, Poisson(5) PVs x Poisson(40) tracks, 1 mrad MS/plane, "
+                        f"noise p={w.noise_p:g} (~3k clusters/event), seed {w.seed}",
+            "events": E,
+            "pixels_per_event": n_pix / E,
+            "clusters_per_event": n_clu / E,
+            "tracks_per_event": T / E,
+            "mode": args.mode,
+            "launch": {"threads_per_event": th, "tile": tl},
+        },
+        "efficiency": m["efficiency"],
+        "ghost_rate": m["ghost_rate"],
+        "clone_rate": m["clone_rate"],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "path_hbm_frac": path_bytes / E * value / (HBM_PEAK_GBS * 1e9),
+        "stages_ms": stages,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/* velo.h -- C ABI of the MI355X VELO hot path (libvelo.so).
+ *
+ * The library reconstructs vertex-detector (VELO) track segments of the first
+ * software-trigger stage described in arXiv 2412.05041 (section "HLT1 details
+ * and results": a simplified pattern recognition, a fit of the VELO segment
+ * only, hits taken by one pass removed before the next, candidates kept when
+ * they have enough hits and a low chi2).  The paper does not spell out the
+ * steps; the library implements this reading:
+ *
+ *   velo_cluster      8-connected pixel clusters per (event, plane), numbered by
+ *                     smallest pixel id, binary centroid;
+ *   velo_find_tracks  triplet seeding on consecutive planes (downstream first),
+ *                     greedy claiming by miss distance, plane-by-plane
+ *                     extension, chi2 (or learned) acceptance;
+ *   velo_fit          least-squares straight-line fit of each track;
+ *   velo_pipeline     the three steps in one stream-ordered call (persistent
+ *                     work-stealing kernels, captured once in a HIP graph);
+ *   velo_mlp_*        the learned ghost filter (10 -> 32 -> 32 -> 1, BF16 MFMA,
+ *                     FP32 accumulation) and its on-GPU training step.
+ *
+ * Conventions
+ *   - Every d_* argument is a DEVICE pointer owned by the caller; it must stay
+ *     valid until the work queued on `stream` has finished.  `stream` is a
+ *     hipStream_t (NULL = default stream).  Host pointers are named h_*.
+ *   - Calls only enqueue work: they never synchronise, except velo_status_read
+ *     and velo_autotune, which say so.
+ *   - The return value reports argument validation and launch errors only
+ *     (VELO_OK or a negative VELO_ERR_*).  Data-dependent problems (capacity
+ *     overflow, malformed input) are written asynchronously to d_status:
+ *       d_status[0]             worst severity (0 ok, 1 overflow, 2 bad input)
+ *       d_status[1..4]          required clusters, tracks, track hits, pixels
+ *       d_status[5]             events processed by the large-event path
+ *       d_status[6]             tracks decided by the plain-cut fallback
+ *       d_status[7]             reserved
+ *       d_status[8 + e]         flags of event e (VELO_EV_*)
+ *     so d_status holds VELO_STATUS_WORDS(n_events) int32.  On overflow every
+ *     offset array is still complete and exact; element arrays are written only
+ *     below their capacity.
+ *   - A context is used from one host thread and one stream at a time.
+ *   - Layouts: events x 26 planes in CSR form.  pix_id = row*1454 + column,
+ *     strictly ascending inside an (event, plane) segment.  Cluster and track
+ *     indices are global within the batch.
+ */
+#ifndef VELO_H
+#define VELO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VELO_N_PLANES 26
+#define VELO_N_SIDE 1454
+#define VELO_MLP_NPARAM 1441
+#define VELO_MLP_NFEAT 10
+#define VELO_FEAT_STRIDE 16
+#define VELO_STATUS_HDR 8
+#define VELO_STATUS_WORDS(n_events) (VELO_STATUS_HDR + (n_events))
+
+enum velo_error {
+    VELO_OK = 0,
+    VELO_ERR_ARG = -1,          /* invalid argument (null pointer, negative size, ...) */
+    VELO_ERR_NOT_RESERVED = -2, /* velo_reserve was not called or is too small          */
+    VELO_ERR_DEVICE = -3,       /* a HIP call failed; see velo_last_error()             */
+    VELO_ERR_UNSUPPORTED = -4   /* configuration the library does not implement         */
+};
+
+enum velo_event_flag {
+    VELO_EV_OVERFLOW = 1,  /* an output or internal capacity was exceeded: no tracks */
+    VELO_EV_BAD_INPUT = 2, /* malformed pixel input (validate mode)                   */
+    VELO_EV_LARGE_PATH = 4, /* processed by the large-event (global memory) path      */
+    VELO_EV_FALLBACK = 8   /* learned mode: some decision used the plain cut          */
+};
+
+enum velo_track_flag {
+    VELO_TRK_PLAIN_ACCEPT = 1, /* chi2/ndof cut passed                    */
+    VELO_TRK_LEARNED = 2,      /* learned mode was active                 */
+    VELO_TRK_FALLBACK = 4,     /* learned mode fell back to the plain cut */
+    VELO_TRK_ACCEPT = 8        /* final decision                          */
+};
+
+/* Detector geometry.  plane_z strictly ascending (mm, FP32). */
+typedef struct velo_geometry {
+    int32_t n_planes; /* must be VELO_N_PLANES */
+    float plane_z[VELO_N_PLANES];
+} velo_geometry;
+
+/* Cut set of the track finder.  All comparisons are FP32, evaluated in the
+ * order documented in the design doc, with no fused multiply-add. */
+typedef struct velo_cuts {
+    float t_max;      /* seed: |tx| <= t_max and |ty| <= t_max                     */
+    float d2_max;     /* seed: squared closest approach of its line to the z axis  */
+    float s_max;      /* seed: squared miss distance of the middle hit             */
+    float e_max;      /* extension: squared miss distance of an added hit          */
+    int32_t max_skip; /* planes a track may skip while being extended              */
+    float c3;         /* chi2/ndof bound of 3-hit tracks                           */
+    float c4;         /* chi2/ndof bound of tracks with >= 4 hits                  */
+    float sigma;      /* hit resolution of the fit (mm)                            */
+    int32_t mode;     /* 0 plain chi2 cut, 1 learned filter                        */
+    float logit_band; /* learned: |logit| < band falls back to the plain cut      */
+} velo_cuts;
+
+typedef struct velo_ctx velo_ctx;
+
+/* Creates a context on HIP device `device` (made current for the call).
+ * Validates the geometry (ascending z, 26 planes) and cuts (finite, >= 0). */
+int velo_create(const velo_geometry* geometry, const velo_cuts* cuts, int device, velo_ctx** out);
+void velo_destroy(velo_ctx* ctx);
+int velo_set_cuts(velo_ctx* ctx, const velo_cuts* cuts);
+
+/* 1 = check pixel inputs (ids < 1454^2, strictly ascending per segment) and
+ * flag VELO_EV_BAD_INPUT instead of clustering malformed segments. */
+int velo_set_validate(velo_ctx* ctx, int32_t on);
+
+/* The only call that allocates device memory (the internal workspace).  Must be
+ * made before any other enqueue and before stream capture; may be repeated to
+ * grow.  max_clusters bounds the clusters of a batch (<= max_pixels). */
+int velo_reserve(velo_ctx* ctx, int32_t max_events, int64_t max_pixels, int64_t max_clusters);
+
+/* Pixel clustering (connected components, 8-neighbourhood).
+ *   in : d_pix_off[n_events*26+1] int32, d_pix_id[...] uint32
+ *   out: d_pix_clu[n_pix] global cluster index of each pixel,
+ *        d_clu_off[n_events*26+1], d_clu_x/d_clu_y[clu_cap] centroid (mm),
+ *        d_clu_npix[clu_cap] (nullable) pixels per cluster.
+ * Cluster x = ((float)sum_col / (float)n - 726.5f) * 0.055f, likewise y. */
+int velo_cluster(velo_ctx* ctx, int32_t n_events, const int32_t* d_pix_off, const uint32_t* d_pix_id,
+                 int32_t* d_pix_clu, int32_t* d_clu_off, float* d_clu_x, float* d_clu_y,
+                 int32_t* d_clu_npix, int64_t clu_cap, int32_t* d_status, void* stream);
+
+/* Track finding on clusters (CSR per event and plane, as velo_cluster writes).
+ *   out: d_trk_off[n_events+1], d_trk_hit_off[trk_cap+1], d_trk_hit[hit_cap]
+ *        (global cluster indices, plane ascending), d_trk_planes[trk_cap]
+ *        (bit k = hit on plane k), d_trk_flags[trk_cap] (nullable, VELO_TRK_*),
+ *        d_trk_logit[trk_cap] (nullable, learned mode).
+ * Tracks of an event are in creation order.  emit_rejected = 1 writes every
+ * candidate with its flags instead of the accepted tracks only. */
+int velo_find_tracks(velo_ctx* ctx, int32_t n_events, const int32_t* d_clu_off, const float* d_clu_x,
+                     const float* d_clu_y, int32_t* d_trk_off, int32_t* d_trk_hit_off, int32_t* d_trk_hit,
+                     uint32_t* d_trk_planes, uint8_t* d_trk_flags, float* d_trk_logit, int64_t trk_cap,
+                     int64_t hit_cap, int32_t emit_rejected, int32_t* d_status, void* stream);
+
+/* Straight-line least-squares fit (x-z and y-z), centred at the hit centroid.
+ *   d_n_tracks (nullable): device count of tracks; when given, only that many
+ *   (at most max_tracks) are fitted, which keeps the call free of host syncs.
+ *   out: d_par[max_tracks][8] = x_ref, y_ref, z_ref, tx, ty, chi2, ndof, 0. */
+int velo_fit(velo_ctx* ctx, int64_t max_tracks, const int32_t* d_n_tracks, const int32_t* d_trk_hit_off,
+             const int32_t* d_trk_hit, const uint32_t* d_trk_planes, const float* d_clu_x,
+             const float* d_clu_y, float* d_par, void* stream);
+
+/* The whole path (cluster -> find -> fit) in one call.  Output identical to
+ * velo_cluster + velo_find_tracks + velo_fit.  The kernels are captured into a
+ * HIP graph on first use for a given argument set and replayed afterwards. */
+int velo_pipeline(velo_ctx* ctx, int32_t n_events, const int32_t* d_pix_off, const uint32_t* d_pix_id,
+                  int32_t* d_pix_clu, int32_t* d_clu_off, float* d_clu_x, float* d_clu_y,
+                  int64_t clu_cap, int32_t* d_trk_off, int32_t* d_trk_hit_off, int32_t* d_trk_hit,
+                  uint32_t* d_trk_planes, uint8_t* d_trk_flags, float* d_trk_logit, float* d_par,
+                  int64_t trk_cap, int64_t hit_cap, int32_t* d_status, void* stream);
+
+/* Stage timing.  With timing on, velo_pipeline runs its kernels eagerly (no
+ * graph) with HIP events recorded on `stream` between the stages; after the
+ * call velo_last_timing synchronises the stream and returns the durations (ms)
+ * of the VELO_N_STAGES stages: reset, cluster+staging, event order, finder
+ * (LDS tiles), finder (large events), learned decision, scan, output+fit. */
+#define VELO_N_STAGES 8
+int velo_set_timing(velo_ctx* ctx, int32_t on);
+int velo_last_timing(velo_ctx* ctx, float* h_ms, int32_t n);
+
+/* Launch configuration of the track finder: threads per event (64, 128, 256)
+ * and LDS tile (0 small, 1 medium, 2 large).  Outputs never depend on it. */
+int velo_set_launch(velo_ctx* ctx, int32_t threads, int32_t tile);
+int velo_get_launch(velo_ctx* ctx, int32_t* threads, int32_t* tile);
+
+/* Times every launch configuration on the given clusters (device inputs, as
+ * for velo_find_tracks) and keeps the fastest.  Synchronises the stream.
+ * h_ms (nullable) receives the 9 timings, configuration-major. */
+int velo_autotune(velo_ctx* ctx, int32_t n_events, const int32_t* d_clu_off, const float* d_clu_x,
+                  const float* d_clu_y, int32_t reps, float* h_ms, void* stream);
+
+/* Learned filter.  Parameters: 1441 FP32 master weights in the order
+ * W1[32][10], b1[32], W2[32][32], b2[32], w3[32], b3; normalisation: 10 means
+ * then 10 standard deviations.  Both are copied (host pointers). */
+int velo_mlp_set_weights(velo_ctx* ctx, const float* h_master, const float* h_norm);
+int velo_mlp_get_weights(velo_ctx* ctx, float* h_master, float* h_norm);
+
+/* Features of candidates: d_feat[n][16] BF16 bit patterns, standardised
+ * ((f - mean) / sd, FP32, round to nearest even), 10 used, 6 zero. */
+int velo_features(velo_ctx* ctx, int64_t n_tracks, const int32_t* d_trk_hit_off, const int32_t* d_trk_hit,
+                  const uint32_t* d_trk_planes, const float* d_clu_x, const float* d_clu_y,
+                  uint16_t* d_feat, float* d_feat_f32 /* nullable [n][10] raw FP32 */, void* stream);
+
+/* Logits of n feature rows (BF16 MFMA, FP32 accumulation). */
+int velo_mlp_forward(velo_ctx* ctx, int64_t n, const uint16_t* d_feat, float* d_logit, void* stream);
+
+/* Gradient of the mean BCE-with-logits loss (label 1 = ghost) w.r.t. the 1441
+ * parameters, deterministic (fixed-order reduction).  d_grad[1441] FP32,
+ * d_loss (nullable) FP32. */
+int velo_mlp_grad(velo_ctx* ctx, int64_t n, const uint16_t* d_feat, const uint8_t* d_label, float* d_grad,
+                  float* d_loss, void* stream);
+
+/* One training step: gradient as above, then Adam (beta1, beta2, eps as set
+ * by velo_mlp_set_adam; lr given) on the FP32 master weights. */
+int velo_mlp_train_step(velo_ctx* ctx, int64_t n, const uint16_t* d_feat, const uint8_t* d_label, float lr,
+                        float* d_loss, void* stream);
+int velo_mlp_set_adam(velo_ctx* ctx, float beta1, float beta2, float eps);
+
+/* Optimiser state for checkpoints: master[1441], m[1441], v[1441], step. */
+int velo_mlp_get_state(velo_ctx* ctx, float* h_master, float* h_m, float* h_v, int64_t* h_step);
+int velo_mlp_set_state(velo_ctx* ctx, const float* h_master, const float* h_m, const float* h_v, int64_t step);
+
+/* Synchronises `stream` and copies `n_words` status words to the host. */
+int velo_status_read(velo_ctx* ctx, const int32_t* d_status, int32_t* h_status, int32_t n_words, void* stream);
+
+const char* velo_status_string(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char* velo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VELO_H */

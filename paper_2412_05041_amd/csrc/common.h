@@ -1,0 +1,120 @@
+// common.h -- device-side shared definitions of libvelo (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace velo {
+
+constexpr int kPlanes = 26;
+constexpr int kSide = 1454;
+constexpr int kStatusHdr = 8;
+constexpr int kWave = 64;
+constexpr int kKeyBits = 16;          // azimuth key resolution
+constexpr int kBuckets = 1024;        // counting-sort buckets of large segments (top 10 key bits)
+
+// Cut set + plane positions, passed by value to every kernel that needs them.
+struct Params {
+    float t_max, d2_max, s_max, e_max;
+    int max_skip;
+    float c3, c4, sigma;
+    int mode;
+    float logit_band;
+    float z[kPlanes];
+    // conservative search radii derived on the host (pruning only, never decisive)
+    float r_seed;   // >= sqrt(d2_max)
+    float r_mid;    // >= sqrt(s_max)
+    float r_ext;    // >= sqrt(e_max)
+};
+
+enum : int { EV_OVERFLOW = 1, EV_BAD_INPUT = 2, EV_LARGE = 4, EV_FALLBACK = 8 };
+enum : int { TRK_PLAIN = 1, TRK_LEARNED = 2, TRK_FALLBACK = 4, TRK_ACCEPT = 8 };
+enum : int { ST_SEVERITY = 0, ST_NCLU = 1, ST_NTRK = 2, ST_NHIT = 3, ST_NPIX = 4, ST_NLARGE = 5,
+             ST_NFALLBACK = 6 };
+
+// Device workspace (allocated by velo_reserve).  Per-cluster arrays are indexed
+// by global cluster index; per-candidate arrays by candidate slot, where the
+// candidates of event e occupy [clu_off[26 e], clu_off[26 e] + n_cand(e)).
+struct Work {
+    // azimuth-sorted staging of each (event, plane): x, y, key, global cluster index
+    float* sx;
+    float* sy;
+    uint16_t* skey;
+    int32_t* sid;
+    uint8_t* used;        // per staged position: hit taken
+    // candidates
+    int32_t* chits;       // [slot][26] global cluster index of the hit on each plane
+    uint32_t* cmask;      // planes bitmask
+    uint8_t* cflags;      // TRK_* flags
+    float* clogit;
+    uint16_t* cfeat;      // [slot][16] BF16 standardised features
+    // per event
+    int32_t* ev_ncand;    // candidates
+    int32_t* ev_nout;     // tracks to output
+    int32_t* ev_nouthit;  // hits of those tracks
+    int32_t* ev_tbase;    // exclusive scans of ev_nout / ev_nouthit
+    int32_t* ev_hbase;
+    int32_t* order;       // event processing order (largest first)
+    int32_t* large;       // events for the large-event path
+    uint64_t* lookback;   // decoupled look-back words of the cluster kernel
+    int32_t* counters;    // [0] cluster tickets, [1] finder events, [2] #large, [3] large tickets,
+                          // [4] spin timeouts, [5..7] spare
+    // large-event path, per cluster (global cluster index)
+    int32_t* g_claim;
+    uint64_t* g_slota;
+    uint32_t* g_slotb;
+    float* g_ttx;         // track state, per candidate slot
+    float* g_tty;
+    float* g_txb;
+    float* g_tyb;
+    int32_t* g_tkb;
+    int32_t* g_twant;
+    // large-event seed pool: per block of the large kernel
+    float* p_q;
+    int32_t* p_h;         // [entry][3] staged positions
+    uint8_t* p_alive;
+    int64_t pool_cap;     // entries per block
+    int32_t n_large_blocks;
+    // cluster kernel global path scratch, per pixel
+    int32_t* g_par;
+    uint32_t* g_sc;
+    uint32_t* g_sr;
+    uint32_t* g_cnt;
+    int32_t* g_tmp;
+    int64_t cap_clusters, cap_pixels;
+    int64_t cap_scratch;  // entries of the per-pixel scratch (max of pixels, clusters)
+    int32_t cap_events;
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Monotone azimuth key: floor((phi + pi) * 2^16 / (2 pi)), clamped.  Used only
+// to order hits for window searches; every decision uses the exact cuts.
+__device__ __forceinline__ int phi_key(float phi) {
+    const float u = (phi + 3.14159265358979f) * 10430.378350470453f;
+    int k = (int)u;
+    k = k < 0 ? 0 : k;
+    return k > 65535 ? 65535 : k;
+}
+
+__device__ __forceinline__ void atomic_max_i32(int32_t* p, int32_t v) { atomicMax(p, v); }
+
+__device__ __forceinline__ void set_event_flag(int32_t* status, int e, int flag, int severity) {
+    if (!status) return;
+    atomicOr(status + kStatusHdr + e, flag);
+    atomicMax(status + ST_SEVERITY, severity);
+}
+
+// Wave-wide exclusive prefix sum of v (wave64).
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if (lane_id() >= o) x += y;
+    }
+    *total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+}
+
+}  // namespace velo

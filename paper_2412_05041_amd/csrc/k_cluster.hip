@@ -1,0 +1,345 @@
+// k_cluster.hip -- pixel clustering and azimuth-sorted hit staging.
+//
+// One wave64 workgroup per (event, plane) segment.  Workgroups take segments
+// from a ticket counter in launch order, so the single-pass decoupled look-back
+// that produces the cluster offsets only ever waits on segments that are
+// already running.
+//
+// Clustering = 8-connected components of the fired pixels.  Each pixel unites
+// with its neighbours of smaller id (same row: id-1; previous row: the three
+// ids around id-1454, with the column checked so that rows never wrap).
+// Union-find links the larger root under the smaller with atomicMin, so the
+// surviving root of a component is its smallest index = smallest pixel id.
+// Roots are numbered by a wave prefix sum in index order; integer column/row
+// sums give the centroid x = ((float)sum_c / (float)n - 726.5f) * 0.055f.
+#include "kernels.h"
+
+namespace velo {
+
+namespace {
+
+constexpr int kCap = 512;            // pixels of a segment handled in LDS
+constexpr int kSmallBuckets = 256;   // staging buckets for segments in LDS
+
+template <typename P>
+__device__ __forceinline__ int ld_rlx(P* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename P>
+__device__ __forceinline__ int find_root(P* par, int a) {
+    int p = ld_rlx(par + a);
+    while (p != a) {
+        a = p;
+        p = ld_rlx(par + a);
+    }
+    return a;
+}
+
+template <typename P>
+__device__ __forceinline__ void unite(P* par, int a, int b) {
+    while (true) {
+        a = find_root(par, a);
+        b = find_root(par, b);
+        if (a == b) return;
+        if (a < b) { const int t = a; a = b; b = t; }
+        const int old = atomicMin(par + a, b);
+        if (old == a) return;
+        a = old;  // a gained a parent meanwhile: unite that parent with b
+    }
+}
+
+template <typename Id>
+__device__ __forceinline__ int lower_bound_u32(const Id* a, int n, uint32_t v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename Id, typename P>
+__device__ __forceinline__ void unite_neighbours(const Id* ids, P* par, int i) {
+    const uint32_t id = ids[i];
+    const uint32_t c = id % kSide, r = id / kSide;
+    if (c > 0 && i > 0 && ids[i - 1] == id - 1) unite(par, i, i - 1);
+    if (r == 0) return;
+    const uint32_t lo = id - kSide - (c > 0 ? 1u : 0u);
+    const uint32_t hi = id - kSide + (c < kSide - 1 ? 1u : 0u);
+    for (int j = lower_bound_u32(ids, i, lo); j < i && ids[j] <= hi; ++j) unite(par, i, j);
+}
+
+__device__ __forceinline__ uint64_t lb_load(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back over segments in ticket order: exclusive prefix of
+// `count`.  Lane 0 only.  The wait is bounded: a timeout is counted in
+// counters[4] (a parity failure, never a hang).
+__device__ int64_t lookback(uint64_t* lb, int seg, int64_t count, int32_t* timeouts) {
+    constexpr uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1;
+    if (seg == 0) {
+        lb_store(lb, kInc | (uint64_t)count);
+        return 0;
+    }
+    lb_store(lb + seg, kAgg | (uint64_t)count);
+    int64_t excl = 0;
+    int j = seg - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const uint64_t v = lb_load(lb + j);
+        const uint64_t f = v >> 62;
+        if (f == 0) {
+            if (++spins > (1u << 24)) { atomicAdd(timeouts, 1); break; }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += (int64_t)(v & kVal);
+        if (f == 2) break;
+        --j;
+    }
+    lb_store(lb + seg, kInc | (uint64_t)(excl + count));
+    return excl;
+}
+
+// Azimuth-sorted staging of the m clusters of one segment, by (key, index).
+// kbuf/tbuf: m-element scratch; hist: nb counters (LDS).  Staged entry g =
+// gbase + rank holds x, y, key and the global cluster index gbase + j.
+template <int kNb, typename KB, typename TB>
+__device__ void stage_segment(const float* cx, const float* cy, int m, int64_t gbase, KB* kbuf, TB* tbuf,
+                              uint32_t* hist, const Work& w) {
+    constexpr int kShift = kKeyBits - __builtin_ctz(kNb);
+    const int lane = threadIdx.x;
+    for (int b = lane; b < kNb; b += kWave) hist[b] = 0;
+    __syncthreads();
+    for (int j = lane; j < m; j += kWave) {
+        const int k = phi_key(atan2f(cy[j], cx[j]));
+        kbuf[j] = (uint32_t)k;
+        atomicAdd(hist + (k >> kShift), 1u);
+    }
+    __syncthreads();
+    {
+        constexpr int per = kNb / kWave;
+        uint32_t loc[per];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < per; ++i) { loc[i] = hist[lane * per + i]; s += loc[i]; }
+        int tot;
+        uint32_t run = (uint32_t)wave_excl_scan((int)s, &tot);
+#pragma unroll
+        for (int i = 0; i < per; ++i) { hist[lane * per + i] = run; run += loc[i]; }
+    }
+    __syncthreads();
+    for (int j = lane; j < m; j += kWave) {
+        const uint32_t pos = atomicAdd(hist + (kbuf[j] >> kShift), 1u);
+        tbuf[pos] = j;
+    }
+    __syncthreads();
+    // hist[b] is now the end of bucket b
+    for (int p = lane; p < m; p += kWave) {
+        const int j = tbuf[p];
+        const uint32_t kj = kbuf[j];
+        const int b = (int)(kj >> kShift);
+        const int s = b ? (int)hist[b - 1] : 0, e = (int)hist[b];
+        int r = s;
+        for (int q = s; q < e; ++q) {
+            const int i = tbuf[q];
+            const uint32_t ki = kbuf[i];
+            r += (ki < kj || (ki == kj && i < j)) ? 1 : 0;
+        }
+        const int64_t g = gbase + r;
+        w.sx[g] = cx[j];
+        w.sy[g] = cy[j];
+        w.skey[g] = (uint16_t)kj;
+        w.sid[g] = (int32_t)(gbase + j);
+        w.used[g] = 0;
+    }
+}
+
+// Clustering of one segment.  kSmall: every array in LDS; otherwise the
+// parent/rank/sum arrays live in the per-pixel global scratch.
+template <bool kSmall, typename Id, typename P, typename R>
+__device__ void cluster_segment(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
+                                unsigned long long* s_sum, uint32_t* s_hist, int64_t* s_cbase, int* s_m,
+                                int refuse) {
+    const int lane = threadIdx.x;
+    const Work& w = a.w;
+    const int e = seg / kPlanes;
+
+    // refuse: the segment cannot be clustered (no scratch for it); it then
+    // contributes no clusters and its event is flagged
+    int bad = refuse;
+    if (a.validate && !refuse) {
+        for (int i = lane; i < n; i += kWave) {
+            const uint32_t id = ids[i];
+            if (id >= (uint32_t)(kSide * kSide) || (i > 0 && ids[i - 1] >= id)) bad = 1;
+        }
+    }
+    bad = __syncthreads_or(bad);
+    int m = 0;
+    if (!bad) {
+        for (int i = lane; i < n; i += kWave) par[i] = i;
+        __syncthreads();
+        for (int i = lane; i < n; i += kWave) unite_neighbours(ids, par, i);
+        __syncthreads();
+        for (int i = lane; i < n; i += kWave) rnk[i] = find_root(par, i);
+        __syncthreads();
+        // number the roots in index order; par[root] := its rank
+        for (int c0 = 0; c0 < n; c0 += kWave) {
+            const int i = c0 + lane;
+            const int isroot = (i < n && rnk[i] == i) ? 1 : 0;
+            int tot;
+            const int ex = wave_excl_scan(isroot, &tot);
+            if (isroot) par[i] = m + ex;
+            m += tot;
+        }
+        __syncthreads();
+        for (int i = lane; i < n; i += kWave) rnk[i] = par[rnk[i]];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const int64_t cb = lookback(w.lookback, seg, m, w.counters + 4);
+        a.clu_off[seg] = (int32_t)cb;
+        if (seg == a.n_seg - 1) {
+            a.clu_off[a.n_seg] = (int32_t)(cb + m);
+            if (a.status) {
+                a.status[ST_NCLU] = (int32_t)(cb + m);
+                a.status[ST_NPIX] = a.pix_off[a.n_seg];
+            }
+        }
+        *s_cbase = cb;
+        *s_m = m;
+    }
+    __syncthreads();
+    const int64_t cbase = *s_cbase;
+    if (bad) {
+        for (int i = lane; i < n; i += kWave) a.pix_clu[p0 + i] = -1;
+        if (lane == 0) set_event_flag(a.status, e, refuse ? EV_OVERFLOW : EV_BAD_INPUT, refuse ? 1 : 2);
+        *s_m = -1;
+        return;
+    }
+    const bool fits = cbase + m <= a.clu_cap;
+    if (!fits) {
+        if (lane == 0) set_event_flag(a.status, e, EV_OVERFLOW, 1);
+    }
+    if (kSmall) {
+        for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
+    } else {
+        for (int j = lane; j < m; j += kWave) { w.g_sc[p0 + j] = 0; w.g_sr[p0 + j] = 0; w.g_cnt[p0 + j] = 0; }
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += kWave) {
+        const int rk = rnk[i];
+        a.pix_clu[p0 + i] = (int32_t)(cbase + rk);
+        const uint32_t id = ids[i];
+        const uint32_t c = id % kSide, r = id / kSide;
+        if (kSmall) {
+            // packed [sum_c:32 | count:11 | sum_r:21]; n <= 512 keeps the fields apart
+            atomicAdd(s_sum + rk, ((unsigned long long)c << 32) | (1ull << 21) | (unsigned long long)r);
+        } else {
+            atomicAdd(w.g_sc + p0 + rk, c);
+            atomicAdd(w.g_sr + p0 + rk, r);
+            atomicAdd(w.g_cnt + p0 + rk, 1u);
+        }
+    }
+    __syncthreads();
+    if (fits) {
+        for (int j = lane; j < m; j += kWave) {
+            uint32_t sc, sr, cnt;
+            if (kSmall) {
+                const unsigned long long v = s_sum[j];
+                sc = (uint32_t)(v >> 32);
+                cnt = (uint32_t)((v >> 21) & 0x7ffu);
+                sr = (uint32_t)(v & 0x1fffffu);
+            } else {
+                sc = w.g_sc[p0 + j];
+                sr = w.g_sr[p0 + j];
+                cnt = w.g_cnt[p0 + j];
+            }
+            const float fn = (float)cnt;
+            a.clu_x[cbase + j] = ((float)sc / fn - 726.5f) * 0.055f;
+            a.clu_y[cbase + j] = ((float)sr / fn - 726.5f) * 0.055f;
+            if (a.clu_npix) a.clu_npix[cbase + j] = (int32_t)cnt;
+        }
+    } else if (lane == 0) {
+        *s_m = -1;  // nothing to stage
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
+    __shared__ uint32_t s_id[kCap];
+    __shared__ int32_t s_par[kCap];
+    __shared__ int32_t s_rnk[kCap];
+    __shared__ unsigned long long s_sum[kCap];  // also the 2048-bucket histogram of large segments
+    __shared__ uint32_t s_hist[kSmallBuckets];
+    __shared__ int64_t s_cbase;
+    __shared__ int s_seg, s_m;
+    static_assert(sizeof(s_sum) >= kBuckets * sizeof(uint32_t), "histogram overlay");
+    const Work& w = a.w;
+    if (threadIdx.x == 0) s_seg = atomicAdd(w.counters + 0, 1);
+    __syncthreads();
+    const int seg = s_seg;
+    if (seg >= a.n_seg) return;
+    const int p0 = a.pix_off[seg];
+    const int n = a.pix_off[seg + 1] - p0;
+    const bool small = n <= kCap;
+    if (small) {
+        for (int i = threadIdx.x; i < n; i += kWave) s_id[i] = a.pix_id[p0 + i];
+        __syncthreads();
+        cluster_segment<true>(a, seg, p0, n, s_id, s_par, s_rnk, s_sum, s_hist, &s_cbase, &s_m, 0);
+    } else {
+        // the per-pixel scratch covers pixel positions below its capacity
+        const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
+        cluster_segment<false>(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, s_sum, s_hist,
+                               &s_cbase, &s_m, refuse);
+    }
+    if (!a.stage) return;
+    __syncthreads();
+    const int m = s_m;
+    if (m <= 0) return;
+    const int64_t cb = s_cbase;
+    if (m <= kCap) {
+        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_id, s_rnk, s_hist, w);
+    } else {
+        stage_segment<kBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0,
+                                (uint32_t*)s_sum, w);
+    }
+}
+
+// Staging alone (velo_find_tracks on caller-provided clusters): one wave per segment.
+__global__ __launch_bounds__(kWave) void k_stage(StageArgs a) {
+    __shared__ uint32_t s_k[kCap];
+    __shared__ int32_t s_t[kCap];
+    __shared__ uint32_t s_hist[kBuckets];
+    const int seg = blockIdx.x;
+    if (seg >= a.n_seg) return;
+    const int64_t cb = a.clu_off[seg];
+    const int m = a.clu_off[seg + 1] - (int)cb;
+    if (m <= 0 || cb + m > a.w.cap_clusters) return;  // the finder flags such events
+    if (m <= kCap) {
+        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_k, s_t, s_hist, a.w);
+    } else {
+        stage_segment<kBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, (uint32_t*)(a.w.g_par + cb), a.w.g_tmp + cb,
+                                s_hist, a.w);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s) {
+    if (a.n_seg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cluster, dim3(a.n_seg), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+    if (a.n_seg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stage, dim3(a.n_seg), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace velo

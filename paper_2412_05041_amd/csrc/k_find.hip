@@ -1,0 +1,777 @@
+// k_find.hip -- track finding: triplet seeding + plane-by-plane extension.
+//
+// One workgroup owns one event at a time and walks the planes from the most
+// downstream one (k = 25) to the most upstream one (k = 0).  At step k:
+//   T1  every open track is extended onto plane k: its line (through its two
+//       most upstream hits) is evaluated at z_k and the closest unused hit with
+//       squared miss distance q <= e_max is wanted (ties: lower hit index); a
+//       hit wanted by several tracks goes to the lowest track index.  A track
+//       stays open while it has skipped at most max_skip planes.
+//   T2  seeds: every triplet (h0 on k, h1 on k+1, h2 on k+2) of unused hits
+//       with |tx|,|ty| <= t_max, pointing outward and passing within
+//       sqrt(d2_max) of the beam axis, and with middle-hit miss q <= s_max, is a
+//       candidate.  Candidates are accepted greedily by (q, h0, h1, h2) when
+//       all three hits are still free; accepted seeds become tracks with
+//       consecutive indices in that order.
+//   T3  the new tracks are extended downstream (planes k+3 .. 25) in lockstep,
+//       with the same rule as T1.
+// After the last plane every track is fitted (least squares, FP32) and
+// accepted when chi2/ndof <= c3 (3 hits) or c4.  Every expression follows the
+// oracle's order of operations; the device code is built without contraction.
+//
+// Parallel formulation (identical results):
+//   * hits of each plane are staged sorted by azimuth; a candidate search only
+//     visits hits whose azimuth lies in a window that provably contains every
+//     hit passing the exact cut (plus a margin far above rounding), and the
+//     exact FP32 cut then decides;
+//   * T1/T3 conflicts: atomicMin of the track index on the wanted hit;
+//   * T2 greedy: rounds of "every candidate that holds the smallest key on all
+//     three of its hits wins" (two-phase 64/32-bit atomicMin on (q, h0) then
+//     (h1, h2)), which accepts exactly the candidates the sequential greedy
+//     accepts; winners are then ranked by key for their track indices.
+#include "fitfeat.h"
+#include "kernels.h"
+
+namespace velo {
+
+namespace {
+
+constexpr float kPi = 3.14159265358979f;
+constexpr float kTwoPi = 6.28318530717959f;
+constexpr int kIntMax = 0x7fffffff;
+
+// ---------------------------------------------------------------- storage
+// Accessors hide where a workgroup keeps its per-event state: the LDS tile
+// (normal events) or global scratch (large events).
+
+template <int kP, int kT, int kC>
+struct Tile {
+    float wx[3][kP];
+    float wy[3][kP];
+    int32_t wid[3][kP];
+    uint64_t slota[3][kP];
+    uint32_t slotb[3][kP];
+    int32_t claim[kP];
+    int32_t claimT[kP];
+    uint16_t wk[3][kP];
+    uint8_t wu[3][kP];
+    float ttx[kT], tty[kT], txb[kT], tyb[kT];
+    uint32_t tmask[kT];
+    int32_t twant[kT];
+    int8_t tkb[kT];
+    float cq[kC];
+    uint16_t cp[kC][3];
+    uint8_t calive[kC];
+};
+
+struct Scalars {
+    int n_tracks, n_cand, n_acc, abort, any, event, nout, nouthit;
+    int wn[3];
+    int64_t wg[3];
+    int64_t cb[kPlanes + 1];  // global cluster offsets of the event's planes
+    uint32_t hist[256];
+};
+
+template <int kP, int kT, int kC>
+struct LdsStore {
+    static constexpr bool kLarge = false;
+    Tile<kP, kT, kC>* t;
+    Scalars* s;
+    const Work* w;
+    int64_t slot0;
+    __device__ float X(int sl, int i) const { return t->wx[sl][i]; }
+    __device__ float Y(int sl, int i) const { return t->wy[sl][i]; }
+    __device__ int K(int sl, int i) const { return t->wk[sl][i]; }
+    __device__ int ID(int sl, int i) const { return t->wid[sl][i]; }
+    __device__ uint8_t& U(int sl, int i) { return t->wu[sl][i]; }
+    __device__ int32_t* claim(int sl) { return t->claim; }
+    __device__ int32_t* claimT(int64_t) { return t->claimT; }
+    __device__ uint64_t* slotA(int sl) { return t->slota[sl]; }
+    __device__ uint32_t* slotB(int sl) { return t->slotb[sl]; }
+    __device__ float& ttx(int i) { return t->ttx[i]; }
+    __device__ float& tty(int i) { return t->tty[i]; }
+    __device__ float& txb(int i) { return t->txb[i]; }
+    __device__ float& tyb(int i) { return t->tyb[i]; }
+    __device__ int tkb(int i) const { return t->tkb[i]; }
+    __device__ void set_tkb(int i, int v) { t->tkb[i] = (int8_t)v; }
+    __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
+    __device__ int32_t& twant(int i) { return t->twant[i]; }
+    __device__ float& cq(int i) { return t->cq[i]; }
+    __device__ int cp(int i, int j) const { return t->cp[i][j]; }
+    __device__ void set_cp(int i, int a, int b, int c) { t->cp[i][0] = (uint16_t)a; t->cp[i][1] = (uint16_t)b; t->cp[i][2] = (uint16_t)c; }
+    __device__ uint8_t& calive(int i) { return t->calive[i]; }
+    __device__ uint64_t* wkey64() { return &t->slota[0][0]; }  // winner keys (after the rounds)
+    __device__ uint32_t* wtmp() { return &t->slotb[0][0]; }
+    __device__ int cap_tracks() const { return kT; }
+    __device__ int cap_cand() const { return kC; }
+    __device__ int cap_plane() const { return kP; }
+};
+
+struct GlobalStore {
+    static constexpr bool kLarge = true;
+    Scalars* s;
+    const Work* w;
+    int64_t slot0;   // first candidate slot of the event
+    int64_t pool0;   // first seed-pool entry of this workgroup
+    int cap_t;
+    __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
+    __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
+    __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
+    __device__ int ID(int sl, int i) const { return w->sid[s->wg[sl] + i]; }
+    __device__ uint8_t& U(int sl, int i) { return w->used[s->wg[sl] + i]; }
+    __device__ int32_t* claim(int sl) { return w->g_claim + s->wg[sl]; }
+    __device__ int32_t* claimT(int64_t g) { return w->g_claim + g; }
+    __device__ uint64_t* slotA(int sl) { return w->g_slota + s->wg[sl]; }
+    __device__ uint32_t* slotB(int sl) { return w->g_slotb + s->wg[sl]; }
+    __device__ float& ttx(int i) { return w->g_ttx[slot0 + i]; }
+    __device__ float& tty(int i) { return w->g_tty[slot0 + i]; }
+    __device__ float& txb(int i) { return w->g_txb[slot0 + i]; }
+    __device__ float& tyb(int i) { return w->g_tyb[slot0 + i]; }
+    __device__ int tkb(int i) const { return w->g_tkb[slot0 + i]; }
+    __device__ void set_tkb(int i, int v) { w->g_tkb[slot0 + i] = v; }
+    __device__ uint32_t& tmask(int i) { return w->cmask[slot0 + i]; }
+    __device__ int32_t& twant(int i) { return w->g_twant[slot0 + i]; }
+    __device__ float& cq(int i) { return w->p_q[pool0 + i]; }
+    __device__ int cp(int i, int j) const { return w->p_h[(pool0 + i) * 3 + j]; }
+    __device__ void set_cp(int i, int a, int b, int c) {
+        int32_t* h = w->p_h + (pool0 + i) * 3;
+        h[0] = a; h[1] = b; h[2] = c;
+    }
+    __device__ uint8_t& calive(int i) { return w->p_alive[pool0 + i]; }
+    __device__ uint64_t* wkey64() { return w->g_slota + s->wg[0]; }
+    __device__ uint32_t* wtmp() { return w->g_slotb + s->wg[0]; }
+    __device__ int cap_tracks() const { return cap_t; }
+    __device__ int cap_cand() const { return (int)w->pool_cap; }
+    __device__ int cap_plane() const { return 65535; }
+};
+
+// ---------------------------------------------------------------- windows
+
+// Up to two inclusive key ranges covering azimuths [phi - half, phi + half].
+__device__ __forceinline__ int key_ranges(float phi, float half, int* lo, int* hi) {
+    if (!(half < 3.0f)) { lo[0] = 0; hi[0] = 65535; return 1; }
+    const float a = phi - half, b = phi + half;
+    if (a < -kPi) {
+        lo[0] = phi_key(a + kTwoPi); hi[0] = 65535;
+        lo[1] = 0; hi[1] = phi_key(b);
+        return 2;
+    }
+    if (b > kPi) {
+        lo[0] = phi_key(a); hi[0] = 65535;
+        lo[1] = 0; hi[1] = phi_key(b - kTwoPi);
+        return 2;
+    }
+    lo[0] = phi_key(a); hi[0] = phi_key(b);
+    return 1;
+}
+
+// Window of hits within distance R of the point (ex, ey): half-angle asin(R/r).
+__device__ __forceinline__ int point_window(float ex, float ey, float R, int* lo, int* hi) {
+    const float r = sqrtf(ex * ex + ey * ey);
+    if (!(r > R * 1.001f + 1e-3f)) { lo[0] = 0; hi[0] = 65535; return 1; }
+    const float half = asinf(R / r) * 1.0001f + 2e-4f;
+    return key_ranges(atan2f(ey, ex), half, lo, hi);
+}
+
+template <class KF>
+__device__ __forceinline__ int lower_key(KF key, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (key(mid) < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Visits every position of a key-sorted plane whose key lies in the ranges.
+template <class KF, class F>
+__device__ __forceinline__ void visit(KF key, int n, int nr, const int* lo, const int* hi, F f) {
+    for (int r = 0; r < nr; ++r) {
+        for (int i = lower_key(key, n, lo[r]); i < n && key(i) <= hi[r]; ++i) f(i);
+    }
+}
+
+// ---------------------------------------------------------------- steps
+
+template <int kT, class S>
+__device__ void load_plane(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const int sl = k % 3;
+    if constexpr (!S::kLarge) {
+        // hand the used flags of the plane leaving this slot back to global memory
+        if (k + 3 < kPlanes) {
+            const int64_t g = sc.wg[sl];
+            for (int i = threadIdx.x; i < sc.wn[sl]; i += kT) a.w.used[g + i] = st.U(sl, i);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc.wg[sl] = sc.cb[k];
+        sc.wn[sl] = (int)(sc.cb[k + 1] - sc.cb[k]);
+    }
+    __syncthreads();
+    const int n = sc.wn[sl];
+    const int64_t g = sc.wg[sl];
+    if constexpr (!S::kLarge) {
+        auto* t = st.t;
+        for (int i = threadIdx.x; i < n; i += kT) {
+            t->wx[sl][i] = a.w.sx[g + i];
+            t->wy[sl][i] = a.w.sy[g + i];
+            t->wk[sl][i] = a.w.skey[g + i];
+            t->wid[sl][i] = a.w.sid[g + i];
+            t->wu[sl][i] = 0;
+            t->claim[i] = kIntMax;
+        }
+    }
+    __syncthreads();
+}
+
+// T1: extend open tracks onto plane k.
+template <int kT, class S>
+__device__ void forward(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const int sl = k % 3;
+    const int n = sc.wn[sl];
+    const int nt = sc.n_tracks;
+    const Params& p = a.p;
+    int32_t* claim = st.claim(sl);
+    auto key = [&](int i) { return st.K(sl, i); };
+    for (int t = threadIdx.x; t < nt; t += kT) {
+        int want = -1;
+        const int kb = st.tkb(t);
+        if (n > 0 && kb - k - 1 <= p.max_skip) {
+            const float d = p.z[k] - p.z[kb];
+            const float ex = st.txb(t) + st.ttx(t) * d;
+            const float ey = st.tyb(t) + st.tty(t) * d;
+            int lo[2], hi[2];
+            const int nr = point_window(ex, ey, p.r_ext, lo, hi);
+            float bq = 0.0f;
+            int bid = kIntMax;
+            visit(key, n, nr, lo, hi, [&](int i) {
+                if (st.U(sl, i)) return;
+                const float dx = st.X(sl, i) - ex;
+                const float dy = st.Y(sl, i) - ey;
+                const float q = dx * dx + dy * dy;
+                if (!(q <= p.e_max)) return;
+                const int id = st.ID(sl, i);
+                if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+            });
+            if (want >= 0) atomicMin(claim + want, t);
+        }
+        st.twant(t) = want;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += kT) {
+        const int i = st.twant(t);
+        if (i >= 0 && claim[i] == t) {
+            st.U(sl, i) = 1;
+            const int id = st.ID(sl, i);
+            const float xh = st.X(sl, i), yh = st.Y(sl, i);
+            const int kb = st.tkb(t);
+            const float dz = p.z[kb] - p.z[k];
+            st.ttx(t) = (st.txb(t) - xh) / dz;
+            st.tty(t) = (st.tyb(t) - yh) / dz;
+            st.txb(t) = xh;
+            st.tyb(t) = yh;
+            st.set_tkb(t, k);
+            st.tmask(t) |= 1u << k;
+            a.w.chits[(st.slot0 + t) * kPlanes + k] = id;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += kT) {
+        const int i = st.twant(t);
+        if (i >= 0) claim[i] = kIntMax;
+    }
+    __syncthreads();
+}
+
+// T2 candidate enumeration.  Returns false (uniformly) on candidate overflow.
+template <int kT, class S>
+__device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const Params& p = a.p;
+    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const int n0 = sc.wn[s0], n1 = sc.wn[s1], n2 = sc.wn[s2];
+    if (threadIdx.x == 0) sc.n_cand = 0;
+    __syncthreads();
+    if (n0 == 0 || n1 == 0 || n2 == 0) return true;
+    const float dz2 = p.z[k + 2] - p.z[k];
+    const float dz1 = p.z[k + 1] - p.z[k];
+    const int cap = st.cap_cand();
+    auto key1 = [&](int i) { return st.K(s1, i); };
+    auto key2 = [&](int i) { return st.K(s2, i); };
+    for (int i0 = threadIdx.x; i0 < n0; i0 += kT) {
+        if (st.U(s0, i0)) continue;
+        const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
+        // h2 lies within asin(D / r0) of h0's azimuth (outward line passing within D of the axis)
+        const float r0 = sqrtf(x0 * x0 + y0 * y0);
+        int lo[2], hi[2], nr;
+        if (!(r0 > p.r_seed * 1.001f + 1e-3f)) {
+            lo[0] = 0; hi[0] = 65535; nr = 1;
+        } else {
+            nr = key_ranges(atan2f(y0, x0), asinf(p.r_seed / r0) * 1.0001f + 2e-4f, lo, hi);
+        }
+        visit(key2, n2, nr, lo, hi, [&](int i2) {
+            if (st.U(s2, i2)) return;
+            const float tx = (st.X(s2, i2) - x0) / dz2;
+            const float ty = (st.Y(s2, i2) - y0) / dz2;
+            if (!(fabsf(tx) <= p.t_max && fabsf(ty) <= p.t_max)) return;
+            if (!(x0 * tx + y0 * ty > 0.0f)) return;
+            const float cr = x0 * ty - y0 * tx;
+            if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) return;
+            const float ex = x0 + tx * dz1;
+            const float ey = y0 + ty * dz1;
+            int lo1[2], hi1[2];
+            const int nr1 = point_window(ex, ey, p.r_mid, lo1, hi1);
+            visit(key1, n1, nr1, lo1, hi1, [&](int i1) {
+                if (st.U(s1, i1)) return;
+                const float dx = st.X(s1, i1) - ex;
+                const float dy = st.Y(s1, i1) - ey;
+                const float q = dx * dx + dy * dy;
+                if (!(q <= p.s_max)) return;
+                const int c = atomicAdd(&sc.n_cand, 1);
+                if (c < cap) {
+                    st.cq(c) = q;
+                    st.set_cp(c, i0, i1, i2);
+                    st.calive(c) = 1;
+                }
+            });
+        });
+    }
+    __syncthreads();
+    return sc.n_cand <= cap;
+}
+
+// T2 greedy claiming by rounds of local minima; fills acc[] with the winners.
+template <int kT, class S>
+__device__ void claim_seeds(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const int nc = sc.n_cand;
+    const int64_t b0 = sc.cb[k], b1 = sc.cb[k + 1], b2 = sc.cb[k + 2];
+    uint64_t* A0 = st.slotA(s0);
+    uint64_t* A1 = st.slotA(s1);
+    uint64_t* A2 = st.slotA(s2);
+    uint32_t* B0 = st.slotB(s0);
+    uint32_t* B1 = st.slotB(s1);
+    uint32_t* B2 = st.slotB(s2);
+    for (int sl = 0; sl < 3; ++sl) {
+        uint64_t* A = st.slotA(sl);
+        uint32_t* B = st.slotB(sl);
+        for (int i = threadIdx.x; i < sc.wn[sl]; i += kT) { A[i] = ~0ull; B[i] = ~0u; }
+    }
+    if (threadIdx.x == 0) sc.n_acc = 0;
+    __syncthreads();
+    while (true) {
+        for (int c = threadIdx.x; c < nc; c += kT) {
+            if (st.calive(c) != 1) continue;
+            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) |
+                                (uint32_t)(st.ID(s0, st.cp(c, 0)) - b0);
+            atomicMin((unsigned long long*)(A0 + st.cp(c, 0)), kA);
+            atomicMin((unsigned long long*)(A1 + st.cp(c, 1)), kA);
+            atomicMin((unsigned long long*)(A2 + st.cp(c, 2)), kA);
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < nc; c += kT) {
+            if (st.calive(c) != 1) continue;
+            const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
+            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, i0) - b0);
+            if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA) {
+                const uint32_t kB = ((uint32_t)(st.ID(s1, i1) - b1) << 16) | (uint32_t)(st.ID(s2, i2) - b2);
+                atomicMin(B0 + i0, kB);
+                atomicMin(B1 + i1, kB);
+                atomicMin(B2 + i2, kB);
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < nc; c += kT) {
+            if (st.calive(c) != 1) continue;
+            const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
+            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, i0) - b0);
+            const uint32_t kB = ((uint32_t)(st.ID(s1, i1) - b1) << 16) | (uint32_t)(st.ID(s2, i2) - b2);
+            if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA && B0[i0] == kB && B1[i1] == kB && B2[i2] == kB) {
+                st.calive(c) = 2;  // winner
+                st.U(s0, i0) = 1;
+                st.U(s1, i1) = 1;
+                st.U(s2, i2) = 1;
+            }
+        }
+        __syncthreads();
+        int any = 0;
+        for (int c = threadIdx.x; c < nc; c += kT) {
+            const uint8_t al = st.calive(c);
+            if (al != 1 && al != 2) continue;  // dead, or a winner of an earlier round
+            const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
+            A0[i0] = ~0ull; A1[i1] = ~0ull; A2[i2] = ~0ull;
+            B0[i0] = ~0u; B1[i1] = ~0u; B2[i2] = ~0u;
+            if (al == 2) {
+                st.calive(c) = 3;  // settled winner
+            } else if (st.U(s0, i0) || st.U(s1, i1) || st.U(s2, i2)) {
+                st.calive(c) = 0;
+            } else {
+                any = 1;
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+}
+
+// Rank the winners by (q, h0) -- unique among winners since they share no hit --
+// and create their tracks; then T3.  Returns false on track-capacity overflow.
+template <int kT, class S>
+__device__ bool create_tracks(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const Params& p = a.p;
+    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const int64_t b0 = sc.cb[k];
+    const int t0 = sc.n_tracks;
+    // collect the winners (candidates marked 3)
+    uint64_t* wkey = st.wkey64();
+    uint32_t* wc = st.wtmp();
+    if (threadIdx.x == 0) sc.n_acc = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < sc.n_cand; c += kT) {
+        if (st.calive(c) == 3) {
+            st.calive(c) = 0;
+            wc[atomicAdd(&sc.n_acc, 1)] = (uint32_t)c;
+        }
+    }
+    __syncthreads();
+    const int nw = sc.n_acc;
+    if (t0 + nw > st.cap_tracks()) return false;
+    if (nw == 0) return true;
+    for (int i = threadIdx.x; i < nw; i += kT) {
+        const int c = (int)wc[i];
+        wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, st.cp(c, 0)) - b0);
+    }
+    __syncthreads();
+    // rank by counting (winners per step are few in normal events; the large
+    // path pays O(nw^2 / threads), bounded by the plane size)
+    for (int i = threadIdx.x; i < nw; i += kT) {
+        const uint64_t ki = wkey[i];
+        int r = 0;
+        for (int j = 0; j < nw; ++j) r += wkey[j] < ki ? 1 : 0;
+        const int c = (int)wc[i];
+        const int t = t0 + r;
+        const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
+        const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
+        const float x1 = st.X(s1, i1), y1 = st.Y(s1, i1);
+        // upstream end: b = h0 (plane k), a = h1 (plane k+1)
+        const float dz = p.z[k + 1] - p.z[k];
+        st.ttx(t) = (x1 - x0) / dz;
+        st.tty(t) = (y1 - y0) / dz;
+        st.txb(t) = x0;
+        st.tyb(t) = y0;
+        st.set_tkb(t, k);
+        st.tmask(t) = 7u << k;
+        int32_t* ch = a.w.chits + (st.slot0 + t) * kPlanes;
+        ch[k] = st.ID(s0, i0);
+        ch[k + 1] = st.ID(s1, i1);
+        ch[k + 2] = st.ID(s2, i2);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sc.n_tracks = t0 + nw;
+    __syncthreads();
+
+    // T3: downstream completion of tracks [t0, t0 + nw), planes k+3 .. 25
+    for (int j = k + 3; j < kPlanes; ++j) {
+        const int64_t g = sc.cb[j];
+        const int n = (int)(sc.cb[j + 1] - g);
+        int32_t* claimT = st.claimT(g);
+        if constexpr (!S::kLarge) {
+            for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
+            __syncthreads();
+        }
+        int active = 0;
+        for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
+            int want = -1;
+            const uint32_t m = st.tmask(t);
+            const int kb = 31 - __clz(m);
+            if (j - kb - 1 <= p.max_skip) {
+                active = 1;
+                const int ka = 31 - __clz(m & ~(1u << kb));
+                const int32_t* ch = a.w.chits + (st.slot0 + t) * kPlanes;
+                const float xa = a.clu_x[ch[ka]], ya = a.clu_y[ch[ka]];
+                const float xb = a.clu_x[ch[kb]], yb = a.clu_y[ch[kb]];
+                const float dzab = p.z[ka] - p.z[kb];
+                const float tx = (xa - xb) / dzab;
+                const float ty = (ya - yb) / dzab;
+                const float d = p.z[j] - p.z[kb];
+                const float ex = xb + tx * d;
+                const float ey = yb + ty * d;
+                if (n > 0) {
+                    int lo[2], hi[2];
+                    const int nr = point_window(ex, ey, p.r_ext, lo, hi);
+                    float bq = 0.0f;
+                    int bid = kIntMax;
+                    auto key = [&](int i) { return (int)a.w.skey[g + i]; };
+                    visit(key, n, nr, lo, hi, [&](int i) {
+                        if (a.w.used[g + i]) return;
+                        const float dx = a.w.sx[g + i] - ex;
+                        const float dy = a.w.sy[g + i] - ey;
+                        const float q = dx * dx + dy * dy;
+                        if (!(q <= p.e_max)) return;
+                        const int id = a.w.sid[g + i];
+                        if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+                    });
+                    if (want >= 0) atomicMin(claimT + want, t);
+                }
+            }
+            st.twant(t) = want;
+        }
+        active = __syncthreads_or(active);
+        if (!active) break;
+        for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
+            const int i = st.twant(t);
+            if (i >= 0 && claimT[i] == t) {
+                a.w.used[g + i] = 1;
+                st.tmask(t) |= 1u << j;
+                a.w.chits[(st.slot0 + t) * kPlanes + j] = a.w.sid[g + i];
+            }
+        }
+        __syncthreads();
+        if constexpr (S::kLarge) {
+            for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
+                const int i = st.twant(t);
+                if (i >= 0) claimT[i] = kIntMax;
+            }
+            __syncthreads();
+        }
+    }
+    // the upstream state of the new tracks is unchanged by T3
+    return true;
+}
+
+// T4: fit, plain decision, features.  Writes per-candidate outputs and the
+// event's output counts (plain mode).
+template <int kT, class S>
+__device__ void accept(S& st, const FindArgs& a, int e) {
+    Scalars& sc = *st.s;
+    const Params& p = a.p;
+    const int nt = sc.n_tracks;
+    if (threadIdx.x == 0) { sc.nout = 0; sc.nouthit = 0; }
+    __syncthreads();
+    int my_out = 0, my_hit = 0;
+    for (int t = threadIdx.x; t < nt; t += kT) {
+        const int64_t slot = st.slot0 + t;
+        const uint32_t mask = st.tmask(t);
+        const int32_t* ch = a.w.chits + slot * kPlanes;
+        const FitResult f = fit_track_hits([&](int k, int) { return ch[k]; }, mask, a.clu_x, a.clu_y, p.z, p.sigma);
+        const int n = f.n;
+        const float lim = n == 3 ? p.c3 : p.c4;
+        const bool plain = f.chi2 / (float)f.ndof <= lim;
+        uint8_t fl = plain ? TRK_PLAIN : 0;
+        if (p.mode == 1) {
+            float raw[10];
+            raw_features(f, p.sigma, raw);
+            uint16_t fb[16];
+            std_features(raw, a.mlp_norm, fb);
+            uint4* out = reinterpret_cast<uint4*>(a.w.cfeat + slot * 16);
+            const uint4* src = reinterpret_cast<const uint4*>(fb);
+            out[0] = src[0];
+            out[1] = src[1];
+            fl |= TRK_LEARNED;
+        } else if (plain) {
+            fl |= TRK_ACCEPT;
+        }
+        a.w.cflags[slot] = fl;
+        if constexpr (!S::kLarge) a.w.cmask[slot] = mask;
+        my_out += (fl & TRK_ACCEPT) ? 1 : 0;
+        my_hit += (fl & TRK_ACCEPT) ? n : 0;
+    }
+    atomicAdd(&sc.nout, my_out);
+    atomicAdd(&sc.nouthit, my_hit);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.w.ev_ncand[e] = nt;
+        a.w.ev_nout[e] = sc.nout;
+        a.w.ev_nouthit[e] = sc.nouthit;
+    }
+}
+
+// Whole event.  Returns false when the LDS tile was too small (event must be
+// redone by the large path); on return true the event's outputs are final.
+template <int kT, class S>
+__device__ bool find_event(S& st, const FindArgs& a, int e) {
+    Scalars& sc = *st.s;
+    if (threadIdx.x == 0) {
+        sc.n_tracks = 0;
+        sc.wn[0] = sc.wn[1] = sc.wn[2] = 0;
+        sc.wg[0] = sc.wg[1] = sc.wg[2] = 0;
+    }
+    for (int k = threadIdx.x; k <= kPlanes; k += kT) sc.cb[k] = a.clu_off[e * kPlanes + k];
+    __syncthreads();
+    for (int k = kPlanes - 1; k >= 0; --k) {
+        load_plane<kT>(st, a, k);
+        if (sc.n_tracks > 0) forward<kT>(st, a, k);
+        if (k <= kPlanes - 3) {
+            if (!enumerate_seeds<kT>(st, a, k)) return false;
+            if (sc.n_cand > 0) {
+                claim_seeds<kT>(st, a, k);
+                if (!create_tracks<kT>(st, a, k)) return false;
+            }
+        }
+    }
+    accept<kT>(st, a, e);
+    return true;
+}
+
+__device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) {
+    a.w.ev_ncand[e] = 0;
+    a.w.ev_nout[e] = 0;
+    a.w.ev_nouthit[e] = 0;
+    set_event_flag(a.status, e, flag, 1);
+}
+
+template <int kT, int kP, int kTr, int kC>
+__global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
+    __shared__ Tile<kP, kTr, kC> tile;
+    __shared__ Scalars sc;
+    LdsStore<kP, kTr, kC> st{&tile, &sc, &a.w, 0};
+    while (true) {
+        if (threadIdx.x == 0) {
+            const int i = atomicAdd(a.w.counters + 1, 1);
+            sc.event = i < a.n_events ? a.w.order[i] : -1;
+        }
+        __syncthreads();
+        const int e = sc.event;
+        if (e < 0) return;
+        if (a.clu_off[(e + 1) * kPlanes] > a.clu_limit) {  // clusters not (all) available
+            if (threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
+            __syncthreads();
+            continue;
+        }
+        // admission: every plane must fit the tile
+        int big = 0;
+        for (int k = threadIdx.x; k < kPlanes; k += kT)
+            big |= (a.clu_off[e * kPlanes + k + 1] - a.clu_off[e * kPlanes + k]) > kP;
+        big = __syncthreads_or(big);
+        bool ok = false;
+        if (!big) {
+            st.slot0 = a.clu_off[e * kPlanes];
+            ok = find_event<kT>(st, a, e);
+        }
+        if (!ok && threadIdx.x == 0) {
+            const int i = atomicAdd(a.w.counters + 2, 1);
+            a.w.large[i] = e;
+        }
+        __syncthreads();
+    }
+}
+
+template <int kT>
+__global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
+    __shared__ Scalars sc;
+    GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
+    const int n_large = a.w.counters[2];
+    while (true) {
+        if (threadIdx.x == 0) {
+            const int i = atomicAdd(a.w.counters + 3, 1);
+            sc.event = i < n_large ? a.w.large[i] : -1;
+        }
+        __syncthreads();
+        const int e = sc.event;
+        if (e < 0) return;
+        const int64_t c0 = a.clu_off[e * kPlanes], c1 = a.clu_off[(e + 1) * kPlanes];
+        int too_big = 0;
+        for (int k = threadIdx.x; k < kPlanes; k += kT)
+            too_big |= (a.clu_off[e * kPlanes + k + 1] - a.clu_off[e * kPlanes + k]) > 65535;
+        too_big = __syncthreads_or(too_big);
+        if (threadIdx.x == 0 && a.status) {
+            atomicAdd(a.status + ST_NLARGE, 1);
+            atomicOr(a.status + kStatusHdr + e, EV_LARGE);
+        }
+        if (too_big) {
+            if (threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
+            __syncthreads();
+            continue;
+        }
+        for (int64_t i = c0 + threadIdx.x; i < c1; i += kT) {
+            a.w.used[i] = 0;
+            a.w.g_claim[i] = kIntMax;
+            a.w.g_slota[i] = ~0ull;
+            a.w.g_slotb[i] = ~0u;
+            a.w.cmask[i] = 0;
+        }
+        st.slot0 = c0;
+        st.cap_t = (int)((c1 - c0) / 3 + 1);
+        __syncthreads();
+        const bool ok = find_event<kT>(st, a, e);
+        if (!ok && threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
+        __syncthreads();
+    }
+}
+
+template <int kT, int kP, int kTr, int kC>
+hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC>), dim3(grid), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+
+
+hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
+    hipError_t err = hipSuccess;
+#define VELO_TILE(T, P, TR, C) err = launch_lds<T, P, TR, C>(a, grid, s)
+    switch (threads * 4 + tile) {
+        case 64 * 4 + 0: VELO_TILE(64, 256, 256, 512); break;
+        case 64 * 4 + 1: VELO_TILE(64, 512, 512, 1024); break;
+        case 64 * 4 + 2: VELO_TILE(64, 1024, 768, 1536); break;
+        case 128 * 4 + 0: VELO_TILE(128, 256, 256, 512); break;
+        case 128 * 4 + 1: VELO_TILE(128, 512, 512, 1024); break;
+        case 128 * 4 + 2: VELO_TILE(128, 1024, 768, 1536); break;
+        case 256 * 4 + 0: VELO_TILE(256, 256, 256, 512); break;
+        case 256 * 4 + 1: VELO_TILE(256, 512, 512, 1024); break;
+        case 256 * 4 + 2: VELO_TILE(256, 1024, 768, 1536); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef VELO_TILE
+    return err;
+}
+
+hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_find_large<256>, dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int find_tile_bytes(int threads, int tile) {
+    (void)threads;
+    switch (tile) {
+        case 0: return (int)(sizeof(Tile<256, 256, 512>) + sizeof(Scalars));
+        case 1: return (int)(sizeof(Tile<512, 512, 1024>) + sizeof(Scalars));
+        default: return (int)(sizeof(Tile<1024, 768, 1536>) + sizeof(Scalars));
+    }
+}
+
+}  // namespace velo
+
+namespace velo {
+
+namespace {
+template <int kT, int kP, int kTr, int kC>
+int occ_lds() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess) return 1;
+    return n;
+}
+}  // namespace
+
+int find_blocks_per_cu(int threads, int tile) {
+    switch (threads * 4 + tile) {
+        case 64 * 4 + 0: return occ_lds<64, 256, 256, 512>();
+        case 64 * 4 + 1: return occ_lds<64, 512, 512, 1024>();
+        case 64 * 4 + 2: return occ_lds<64, 1024, 768, 1536>();
+        case 128 * 4 + 0: return occ_lds<128, 256, 256, 512>();
+        case 128 * 4 + 1: return occ_lds<128, 512, 512, 1024>();
+        case 128 * 4 + 2: return occ_lds<128, 1024, 768, 1536>();
+        case 256 * 4 + 0: return occ_lds<256, 256, 256, 512>();
+        case 256 * 4 + 1: return occ_lds<256, 512, 512, 1024>();
+        case 256 * 4 + 2: return occ_lds<256, 1024, 768, 1536>();
+        default: return 1;
+    }
+}
+
+}  // namespace velo

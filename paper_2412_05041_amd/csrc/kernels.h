@@ -1,0 +1,87 @@
+// kernels.h -- kernel argument blocks and host launchers (internal to libvelo).
+#pragma once
+
+#include "common.h"
+
+namespace velo {
+
+struct ClusterArgs {
+    int n_seg;  // events * 26
+    const int32_t* pix_off;
+    const uint32_t* pix_id;
+    int32_t* pix_clu;
+    int32_t* clu_off;
+    float* clu_x;
+    float* clu_y;
+    int32_t* clu_npix;
+    int64_t clu_cap;
+    int32_t* status;
+    int validate;
+    int stage;  // also write the azimuth-sorted staging (fused pipeline)
+    Work w;
+};
+
+struct StageArgs {
+    int n_seg;
+    const int32_t* clu_off;
+    const float* clu_x;
+    const float* clu_y;
+    Work w;
+};
+
+struct FindArgs {
+    int n_events;
+    const int32_t* clu_off;
+    const float* clu_x;
+    const float* clu_y;
+    int32_t* status;
+    Params p;
+    Work w;
+    const float* mlp_master;  // learned mode: FP32 master weights (device)
+    const float* mlp_norm;    // 20 floats
+    int64_t clu_limit;        // events whose clusters reach beyond this are not processed
+};
+
+struct OutArgs {
+    int n_events;
+    const int32_t* clu_off;
+    const float* clu_x;
+    const float* clu_y;
+    int32_t* trk_off;
+    int32_t* trk_hit_off;
+    int32_t* trk_hit;
+    uint32_t* trk_planes;
+    uint8_t* trk_flags;
+    float* trk_logit;
+    float* par;  // fused fit output (nullable)
+    int64_t trk_cap, hit_cap;
+    int emit_rejected;
+    int32_t* status;
+    Params p;
+    Work w;
+};
+
+struct FitArgs {
+    int64_t max_tracks;
+    const int32_t* n_tracks;  // nullable
+    const int32_t* trk_hit_off;
+    const int32_t* trk_hit;
+    const uint32_t* trk_planes;
+    const float* clu_x;
+    const float* clu_y;
+    float* par;
+    Params p;
+};
+
+// launchers (return hipError_t)
+hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_t s);
+hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s);
+hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s);
+hipError_t launch_stage(const StageArgs& a, hipStream_t s);
+hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s);
+hipError_t launch_find_large(const FindArgs& a, hipStream_t s);
+hipError_t launch_scan(const OutArgs& a, hipStream_t s);
+hipError_t launch_output(const OutArgs& a, hipStream_t s);
+hipError_t launch_fit(const FitArgs& a, hipStream_t s);
+
+}  // namespace velo

@@ -1,0 +1,674 @@
+// velo_api.hip -- the C ABI of libvelo: context, workspace, argument checks,
+// stream-ordered launches and the graph-captured pipeline.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/velo.h"
+#include "kernels.h"
+#include "mlp.h"
+
+using namespace velo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(VELO_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+struct GraphKey {
+    std::vector<uintptr_t> v;
+    bool operator==(const GraphKey& o) const { return v == o.v; }
+};
+
+}  // namespace
+
+struct velo_ctx {
+    int device = 0;
+    Params p{};
+    int validate = 0;
+    int threads = 256, tile = 1;
+    Work w{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int n_cu = 0;
+    hipStream_t cap_stream = nullptr;
+    // graph cache of velo_pipeline
+    hipGraphExec_t exec = nullptr;
+    GraphKey key;
+    uint64_t version = 1;  // bumped by anything that changes captured parameters
+    MlpState mlp;
+    // stage timing (eager pipeline)
+    int timing = 0;
+    hipEvent_t ev[VELO_N_STAGES + 1] = {};
+    hipStream_t ev_stream = nullptr;
+    int ev_valid = 0;
+};
+
+namespace {
+
+int check_ctx(velo_ctx* c) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (!c->ws) return fail(VELO_ERR_NOT_RESERVED, "velo_reserve was not called");
+    return VELO_OK;
+}
+
+int set_params(velo_ctx* c, const velo_cuts* cu) {
+    const float v[] = {cu->t_max, cu->d2_max, cu->s_max, cu->e_max, cu->c3, cu->c4, cu->sigma};
+    for (float x : v)
+        if (!(x >= 0.0f) || (std::isinf(x) && x != cu->c3 && x != cu->c4))
+            return fail(VELO_ERR_ARG, "cuts must be finite and >= 0");
+    if (cu->max_skip < 0 || cu->max_skip > 24) return fail(VELO_ERR_ARG, "max_skip out of range");
+    if (cu->mode != 0 && cu->mode != 1) return fail(VELO_ERR_ARG, "mode must be 0 or 1");
+    if (!(cu->sigma > 0.0f)) return fail(VELO_ERR_ARG, "sigma must be > 0");
+    Params& p = c->p;
+    p.t_max = cu->t_max;
+    p.d2_max = cu->d2_max;
+    p.s_max = cu->s_max;
+    p.e_max = cu->e_max;
+    p.max_skip = cu->max_skip;
+    p.c3 = cu->c3;
+    p.c4 = cu->c4;
+    p.sigma = cu->sigma;
+    p.mode = cu->mode;
+    p.logit_band = cu->logit_band;
+    // search radii: generous upper bounds of the cut distances (pruning only)
+    p.r_seed = std::sqrt(cu->d2_max) * 1.0001f + 1e-6f;
+    p.r_mid = std::sqrt(cu->s_max) * 1.0001f + 1e-6f;
+    p.r_ext = std::sqrt(cu->e_max) * 1.0001f + 1e-6f;
+    c->version++;
+    return VELO_OK;
+}
+
+template <typename T>
+T* carve(char*& cur, int64_t n) {
+    cur = (char*)(((uintptr_t)cur + 255) & ~(uintptr_t)255);
+    T* p = (T*)cur;
+    cur += sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    return p;
+}
+
+size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
+    char* cur = base;
+    const int64_t PX = std::max(P, C);
+    w.sx = carve<float>(cur, C);
+    w.sy = carve<float>(cur, C);
+    w.skey = carve<uint16_t>(cur, C);
+    w.sid = carve<int32_t>(cur, C);
+    w.used = carve<uint8_t>(cur, C);
+    w.chits = carve<int32_t>(cur, C * kPlanes);
+    w.cmask = carve<uint32_t>(cur, C);
+    w.cflags = carve<uint8_t>(cur, C);
+    w.clogit = carve<float>(cur, C);
+    w.cfeat = carve<uint16_t>(cur, C * 16);
+    w.ev_ncand = carve<int32_t>(cur, E);
+    w.ev_nout = carve<int32_t>(cur, E);
+    w.ev_nouthit = carve<int32_t>(cur, E);
+    w.ev_tbase = carve<int32_t>(cur, E);
+    w.ev_hbase = carve<int32_t>(cur, E);
+    w.order = carve<int32_t>(cur, E);
+    w.large = carve<int32_t>(cur, E);
+    w.lookback = carve<uint64_t>(cur, (int64_t)E * kPlanes);
+    w.counters = carve<int32_t>(cur, 8);
+    w.g_claim = carve<int32_t>(cur, C);
+    w.g_slota = carve<uint64_t>(cur, C);
+    w.g_slotb = carve<uint32_t>(cur, C);
+    w.g_ttx = carve<float>(cur, C);
+    w.g_tty = carve<float>(cur, C);
+    w.g_txb = carve<float>(cur, C);
+    w.g_tyb = carve<float>(cur, C);
+    w.g_tkb = carve<int32_t>(cur, C);
+    w.g_twant = carve<int32_t>(cur, C);
+    w.n_large_blocks = 32;
+    w.pool_cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 20, C));
+    const int64_t pool = w.pool_cap * w.n_large_blocks;
+    w.p_q = carve<float>(cur, pool);
+    w.p_h = carve<int32_t>(cur, pool * 3);
+    w.p_alive = carve<uint8_t>(cur, pool);
+    w.g_par = carve<int32_t>(cur, PX);
+    w.g_sc = carve<uint32_t>(cur, PX);
+    w.g_sr = carve<uint32_t>(cur, PX);
+    w.g_cnt = carve<uint32_t>(cur, PX);
+    w.g_tmp = carve<int32_t>(cur, PX);
+    w.cap_clusters = C;
+    w.cap_pixels = P;
+    w.cap_scratch = PX;
+    w.cap_events = E;
+    return (size_t)(cur - base) + 256;
+}
+
+int grid_for(velo_ctx* c, int n_events) {
+    const int per_cu = find_blocks_per_cu(c->threads, c->tile);
+    const int g = std::max(1, c->n_cu * std::max(per_cu, 1));
+    return std::max(1, std::min(n_events, g));
+}
+
+// Enqueue the finder (staging must be in place) and the output compaction.
+// Timing mark i (no-op unless the eager timed pipeline is running).
+int mark(velo_ctx* c, int i, hipStream_t s, bool on) {
+    if (on) HIP_OK(hipEventRecord(c->ev[i], s));
+    return VELO_OK;
+}
+
+int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* clu_x, const float* clu_y,
+                     int32_t* trk_off, int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes,
+                     uint8_t* trk_flags, float* trk_logit, float* par, int64_t trk_cap, int64_t hit_cap,
+                     int32_t emit, int32_t* status, int64_t clu_limit, hipStream_t s, bool timed = false) {
+    HIP_OK(launch_order(c->w, E, clu_off, s));
+    if (int rc = mark(c, 3, s, timed)) return rc;
+    FindArgs fa{};
+    fa.n_events = E;
+    fa.clu_off = clu_off;
+    fa.clu_x = clu_x;
+    fa.clu_y = clu_y;
+    fa.status = status;
+    fa.p = c->p;
+    fa.w = c->w;
+    fa.mlp_master = c->mlp.d_master;
+    fa.mlp_norm = c->mlp.d_norm;
+    fa.clu_limit = clu_limit;
+    HIP_OK(launch_find_lds(fa, c->threads, c->tile, grid_for(c, E), s));
+    if (int rc = mark(c, 4, s, timed)) return rc;
+    HIP_OK(launch_find_large(fa, s));
+    if (int rc = mark(c, 5, s, timed)) return rc;
+    if (c->p.mode == 1) HIP_OK(launch_mlp_accept(c->mlp, fa, s));
+    if (int rc = mark(c, 6, s, timed)) return rc;
+    OutArgs oa{};
+    oa.n_events = E;
+    oa.clu_off = clu_off;
+    oa.clu_x = clu_x;
+    oa.clu_y = clu_y;
+    oa.trk_off = trk_off;
+    oa.trk_hit_off = trk_hit_off;
+    oa.trk_hit = trk_hit;
+    oa.trk_planes = trk_planes;
+    oa.trk_flags = trk_flags;
+    oa.trk_logit = trk_logit;
+    oa.par = par;
+    oa.trk_cap = trk_cap;
+    oa.hit_cap = hit_cap;
+    oa.emit_rejected = emit;
+    oa.status = status;
+    oa.p = c->p;
+    oa.w = c->w;
+    HIP_OK(launch_scan(oa, s));
+    if (int rc = mark(c, 7, s, timed)) return rc;
+    HIP_OK(launch_output(oa, s));
+    if (int rc = mark(c, 8, s, timed)) return rc;
+    return VELO_OK;
+}
+
+int check_reserved(velo_ctx* c, int32_t E, int64_t clusters) {
+    if (E < 0) return fail(VELO_ERR_ARG, "n_events < 0");
+    if (E > c->w.cap_events) return fail(VELO_ERR_NOT_RESERVED, "n_events %d > reserved %d", E, c->w.cap_events);
+    if (clusters > c->w.cap_clusters)
+        return fail(VELO_ERR_NOT_RESERVED, "cluster capacity %lld > reserved %lld", (long long)clusters,
+                    (long long)c->w.cap_clusters);
+    return VELO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* velo_last_error(void) { return g_last_error.c_str(); }
+
+const char* velo_status_string(int code) {
+    switch (code) {
+        case VELO_OK: return "ok";
+        case VELO_ERR_ARG: return "invalid argument";
+        case VELO_ERR_NOT_RESERVED: return "workspace not reserved or too small";
+        case VELO_ERR_DEVICE: return "HIP error";
+        case VELO_ERR_UNSUPPORTED: return "unsupported";
+        default: return "unknown";
+    }
+}
+
+int velo_create(const velo_geometry* g, const velo_cuts* cu, int device, velo_ctx** out) {
+    if (!g || !cu || !out) return fail(VELO_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (g->n_planes != kPlanes) return fail(VELO_ERR_ARG, "n_planes must be %d", kPlanes);
+    for (int k = 0; k < kPlanes; ++k) {
+        if (!std::isfinite(g->plane_z[k])) return fail(VELO_ERR_ARG, "plane_z not finite");
+        if (k && !(g->plane_z[k] > g->plane_z[k - 1])) return fail(VELO_ERR_ARG, "plane_z must ascend");
+    }
+    HIP_OK(hipSetDevice(device));
+    velo_ctx* c = new velo_ctx();
+    c->device = device;
+    for (int k = 0; k < kPlanes; ++k) c->p.z[k] = g->plane_z[k];
+    int rc = set_params(c, cu);
+    if (rc) { delete c; return rc; }
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { delete c; return fail(VELO_ERR_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e)); }
+    c->n_cu = prop.multiProcessorCount;
+    e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete c; return fail(VELO_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
+    rc = mlp_init(c->mlp);
+    if (rc) { delete c; return fail(VELO_ERR_DEVICE, "MLP state allocation failed"); }
+    *out = c;
+    return VELO_OK;
+}
+
+void velo_destroy(velo_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->ws) hipFree(c->ws);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    for (int i = 0; i <= VELO_N_STAGES; ++i)
+        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    mlp_free(c->mlp);
+    delete c;
+}
+
+int velo_set_cuts(velo_ctx* c, const velo_cuts* cu) {
+    if (!c || !cu) return fail(VELO_ERR_ARG, "null argument");
+    return set_params(c, cu);
+}
+
+int velo_set_validate(velo_ctx* c, int32_t on) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    c->validate = on ? 1 : 0;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_set_launch(velo_ctx* c, int32_t threads, int32_t tile) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (threads != 64 && threads != 128 && threads != 256) return fail(VELO_ERR_ARG, "threads must be 64/128/256");
+    if (tile < 0 || tile > 2) return fail(VELO_ERR_ARG, "tile must be 0..2");
+    c->threads = threads;
+    c->tile = tile;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_get_launch(velo_ctx* c, int32_t* threads, int32_t* tile) {
+    if (!c || !threads || !tile) return fail(VELO_ERR_ARG, "null argument");
+    *threads = c->threads;
+    *tile = c->tile;
+    return VELO_OK;
+}
+
+int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t max_clusters) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (max_events < 0 || max_pixels < 0 || max_clusters < 0 || max_clusters > max_pixels + 1)
+        return fail(VELO_ERR_ARG, "bad reserve sizes");
+    if (max_pixels >= (int64_t)1 << 31) return fail(VELO_ERR_UNSUPPORTED, "more than 2^31 pixels per batch");
+    if (c->ws && max_events <= c->w.cap_events && max_pixels <= c->w.cap_pixels &&
+        max_clusters <= c->w.cap_clusters)
+        return VELO_OK;
+    HIP_OK(hipSetDevice(c->device));
+    if (c->ws) {
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipFree(c->ws));
+        c->ws = nullptr;
+    }
+    Work w{};
+    const size_t bytes = layout(w, nullptr, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
+                                std::max<int64_t>(max_clusters, 1));
+    void* base = nullptr;
+    HIP_OK(hipMalloc(&base, bytes));
+    layout(w, (char*)base, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
+           std::max<int64_t>(max_clusters, 1));
+    c->w = w;
+    c->ws = base;
+    c->ws_bytes = bytes;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_cluster(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t* pix_id, int32_t* pix_clu,
+                 int32_t* clu_off, float* clu_x, float* clu_y, int32_t* clu_npix, int64_t clu_cap,
+                 int32_t* status, void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    if (E < 0 || !pix_off || !clu_off || (E > 0 && (!pix_id && false)) || clu_cap < 0)
+        return fail(VELO_ERR_ARG, "bad arguments");
+    if (clu_cap > 0 && (!clu_x || !clu_y)) return fail(VELO_ERR_ARG, "null cluster arrays");
+    if (int rc = check_reserved(c, E, 0)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_reset(c->w, E, status, s));
+    ClusterArgs a{};
+    a.n_seg = E * kPlanes;
+    a.pix_off = pix_off;
+    a.pix_id = pix_id;
+    a.pix_clu = pix_clu;
+    a.clu_off = clu_off;
+    a.clu_x = clu_x;
+    a.clu_y = clu_y;
+    a.clu_npix = clu_npix;
+    a.clu_cap = clu_cap;
+    a.status = status;
+    a.validate = c->validate;
+    a.stage = 0;
+    a.w = c->w;
+    if (E == 0) {
+        HIP_OK(hipMemsetAsync(clu_off, 0, sizeof(int32_t), s));
+        return VELO_OK;
+    }
+    HIP_OK(launch_cluster(a, s));
+    return VELO_OK;
+}
+
+int velo_find_tracks(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* clu_x, const float* clu_y,
+                     int32_t* trk_off, int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes,
+                     uint8_t* trk_flags, float* trk_logit, int64_t trk_cap, int64_t hit_cap, int32_t emit,
+                     int32_t* status, void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    if (E < 0 || !clu_off || !trk_off || !trk_hit_off || trk_cap < 0 || hit_cap < 0)
+        return fail(VELO_ERR_ARG, "bad arguments");
+    if (trk_cap > 0 && (!trk_planes || !trk_hit)) return fail(VELO_ERR_ARG, "null track arrays");
+    if (c->p.mode == 1 && !c->mlp.has_weights) return fail(VELO_ERR_ARG, "learned mode needs MLP weights");
+    if (int rc = check_reserved(c, E, 0)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_reset(c->w, E, status, s));
+    StageArgs sa{E * kPlanes, clu_off, clu_x, clu_y, c->w};
+    HIP_OK(launch_stage(sa, s));
+    return enqueue_find_out(c, E, clu_off, clu_x, clu_y, trk_off, trk_hit_off, trk_hit, trk_planes, trk_flags,
+                            trk_logit, nullptr, trk_cap, hit_cap, emit, status, c->w.cap_clusters, s);
+}
+
+int velo_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const int32_t* trk_hit_off,
+             const int32_t* trk_hit, const uint32_t* trk_planes, const float* clu_x, const float* clu_y,
+             float* par, void* stream) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (max_tracks < 0) return fail(VELO_ERR_ARG, "max_tracks < 0");
+    if (max_tracks == 0) return VELO_OK;
+    if (!trk_hit_off || !trk_hit || !trk_planes || !clu_x || !clu_y || !par)
+        return fail(VELO_ERR_ARG, "null argument");
+    FitArgs a{max_tracks, n_tracks, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, par, c->p};
+    HIP_OK(launch_fit(a, (hipStream_t)stream));
+    return VELO_OK;
+}
+
+int velo_pipeline(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t* pix_id, int32_t* pix_clu,
+                  int32_t* clu_off, float* clu_x, float* clu_y, int64_t clu_cap, int32_t* trk_off,
+                  int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes, uint8_t* trk_flags,
+                  float* trk_logit, float* par, int64_t trk_cap, int64_t hit_cap, int32_t* status,
+                  void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    if (E <= 0 || !pix_off || !clu_off || !clu_x || !clu_y || !trk_off || !trk_hit_off || !trk_hit ||
+        !trk_planes || clu_cap < 0 || trk_cap < 0 || hit_cap < 0)
+        return fail(VELO_ERR_ARG, "bad arguments");
+    if (c->p.mode == 1 && !c->mlp.has_weights) return fail(VELO_ERR_ARG, "learned mode needs MLP weights");
+    if (int rc = check_reserved(c, E, std::min<int64_t>(clu_cap, c->w.cap_clusters))) return rc;
+    if (clu_cap > c->w.cap_clusters)
+        return fail(VELO_ERR_NOT_RESERVED, "clu_cap exceeds the reserved cluster capacity");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->timing) {
+        // eager run with events between the stages
+        c->ev_valid = 0;
+        ClusterArgs a{};
+        a.n_seg = E * kPlanes;
+        a.pix_off = pix_off;
+        a.pix_id = pix_id;
+        a.pix_clu = pix_clu;
+        a.clu_off = clu_off;
+        a.clu_x = clu_x;
+        a.clu_y = clu_y;
+        a.clu_npix = nullptr;
+        a.clu_cap = clu_cap;
+        a.status = status;
+        a.validate = c->validate;
+        a.stage = 1;
+        a.w = c->w;
+        if (int rc = mark(c, 0, s, true)) return rc;
+        HIP_OK(launch_reset(c->w, E, status, s));
+        if (int rc = mark(c, 1, s, true)) return rc;
+        HIP_OK(launch_cluster(a, s));
+        if (int rc = mark(c, 2, s, true)) return rc;
+        int rc = enqueue_find_out(c, E, clu_off, clu_x, clu_y, trk_off, trk_hit_off, trk_hit, trk_planes, trk_flags,
+                                  trk_logit, par, trk_cap, hit_cap, 0, status, clu_cap, s, true);
+        if (rc) return rc;
+        c->ev_stream = s;
+        c->ev_valid = 1;
+        return VELO_OK;
+    }
+    GraphKey key;
+    key.v = {(uintptr_t)E, (uintptr_t)pix_off, (uintptr_t)pix_id, (uintptr_t)pix_clu, (uintptr_t)clu_off,
+             (uintptr_t)clu_x, (uintptr_t)clu_y, (uintptr_t)clu_cap, (uintptr_t)trk_off, (uintptr_t)trk_hit_off,
+             (uintptr_t)trk_hit, (uintptr_t)trk_planes, (uintptr_t)trk_flags, (uintptr_t)trk_logit,
+             (uintptr_t)par, (uintptr_t)trk_cap, (uintptr_t)hit_cap, (uintptr_t)status, (uintptr_t)c->version,
+             (uintptr_t)c->mlp.version, (uintptr_t)c->ws};
+    if (!(c->exec && key == c->key)) {
+        if (c->exec) {
+            HIP_OK(hipGraphExecDestroy(c->exec));
+            c->exec = nullptr;
+        }
+        hipStream_t cs = c->cap_stream;
+        HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int rc = VELO_OK;
+        ClusterArgs a{};
+        a.n_seg = E * kPlanes;
+        a.pix_off = pix_off;
+        a.pix_id = pix_id;
+        a.pix_clu = pix_clu;
+        a.clu_off = clu_off;
+        a.clu_x = clu_x;
+        a.clu_y = clu_y;
+        a.clu_npix = nullptr;
+        a.clu_cap = clu_cap;
+        a.status = status;
+        a.validate = c->validate;
+        a.stage = 1;
+        a.w = c->w;
+        if (launch_reset(c->w, E, status, cs) != hipSuccess || launch_cluster(a, cs) != hipSuccess)
+            rc = fail(VELO_ERR_DEVICE, "launch failed during capture");
+        if (!rc)
+            rc = enqueue_find_out(c, E, clu_off, clu_x, clu_y, trk_off, trk_hit_off, trk_hit, trk_planes, trk_flags,
+                                  trk_logit, par, trk_cap, hit_cap, 0, status, clu_cap, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc) { if (g) hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(VELO_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) { c->exec = nullptr; return fail(VELO_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
+        c->key = key;
+    }
+    HIP_OK(hipGraphLaunch(c->exec, s));
+    return VELO_OK;
+}
+
+int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* clu_x, const float* clu_y,
+                  int32_t reps, float* h_ms, void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    if (E <= 0 || !clu_off || !clu_x || !clu_y || reps <= 0) return fail(VELO_ERR_ARG, "bad arguments");
+    if (int rc = check_reserved(c, E, 0)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int threads[3] = {64, 128, 256};
+    float best = 1e30f;
+    int bt = c->threads, bl = c->tile;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    // staging once; the finder leaves it unchanged except for the used flags,
+    // which every event resets when its planes are loaded
+    HIP_OK(launch_reset(c->w, E, nullptr, s));
+    StageArgs sa{E * kPlanes, clu_off, clu_x, clu_y, c->w};
+    HIP_OK(launch_stage(sa, s));
+    int idx = 0;
+    for (int ti = 0; ti < 3; ++ti) {
+        for (int tl = 0; tl < 3; ++tl, ++idx) {
+            c->threads = threads[ti];
+            c->tile = tl;
+            FindArgs fa{};
+            fa.n_events = E;
+            fa.clu_off = clu_off;
+            fa.clu_x = clu_x;
+            fa.clu_y = clu_y;
+            fa.status = nullptr;
+            fa.p = c->p;
+            fa.p.mode = 0;
+            fa.w = c->w;
+            fa.clu_limit = c->w.cap_clusters;
+            float tot = 0.0f;
+            for (int r = 0; r <= reps; ++r) {
+                HIP_OK(launch_reset(c->w, E, nullptr, s));
+                HIP_OK(launch_order(c->w, E, clu_off, s));
+                HIP_OK(hipEventRecord(e0, s));
+                HIP_OK(launch_find_lds(fa, c->threads, c->tile, grid_for(c, E), s));
+                HIP_OK(launch_find_large(fa, s));
+                HIP_OK(hipEventRecord(e1, s));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) tot += ms;  // first run warms up
+            }
+            tot /= (float)reps;
+            if (h_ms) h_ms[idx] = tot;
+            if (tot < best) { best = tot; bt = threads[ti]; bl = tl; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->threads = bt;
+    c->tile = bl;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_set_timing(velo_ctx* c, int32_t on) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (on && !c->ev[0]) {
+        for (int i = 0; i <= VELO_N_STAGES; ++i) HIP_OK(hipEventCreate(&c->ev[i]));
+    }
+    c->timing = on ? 1 : 0;
+    return VELO_OK;
+}
+
+int velo_last_timing(velo_ctx* c, float* h_ms, int32_t n) {
+    if (!c || !h_ms || n < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    if (!c->ev_valid) return fail(VELO_ERR_ARG, "no timed pipeline call");
+    HIP_OK(hipStreamSynchronize(c->ev_stream));
+    for (int i = 0; i < n && i < VELO_N_STAGES; ++i) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        h_ms[i] = ms;
+    }
+    return VELO_OK;
+}
+
+int velo_status_read(velo_ctx* c, const int32_t* d_status, int32_t* h_status, int32_t n_words, void* stream) {
+    if (!c || !d_status || !h_status || n_words < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    HIP_OK(hipMemcpy(h_status, d_status, sizeof(int32_t) * (size_t)n_words, hipMemcpyDeviceToHost));
+    return VELO_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned filter
+extern "C" {
+
+int velo_mlp_set_weights(velo_ctx* c, const float* h_master, const float* h_norm) {
+    if (!c || !h_master || !h_norm) return fail(VELO_ERR_ARG, "null argument");
+    for (int i = 0; i < kNFeat; ++i)
+        if (!(h_norm[kNFeat + i] != 0.0f)) return fail(VELO_ERR_ARG, "normalisation sd must be non-zero");
+    HIP_OK(hipMemcpy(c->mlp.d_master, h_master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->mlp.d_norm, h_norm, sizeof(float) * 2 * kNFeat, hipMemcpyHostToDevice));
+    c->mlp.has_weights = 1;
+    c->mlp.version++;
+    return VELO_OK;
+}
+
+int velo_mlp_get_weights(velo_ctx* c, float* h_master, float* h_norm) {
+    if (!c || !h_master || !h_norm) return fail(VELO_ERR_ARG, "null argument");
+    HIP_OK(hipMemcpy(h_master, c->mlp.d_master, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(h_norm, c->mlp.d_norm, sizeof(float) * 2 * kNFeat, hipMemcpyDeviceToHost));
+    return VELO_OK;
+}
+
+int velo_features(velo_ctx* c, int64_t n, const int32_t* trk_hit_off, const int32_t* trk_hit,
+                  const uint32_t* trk_planes, const float* clu_x, const float* clu_y, uint16_t* feat,
+                  float* feat32, void* stream) {
+    if (!c || n < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    if (n == 0) return VELO_OK;
+    if (!trk_hit_off || !trk_hit || !trk_planes || !clu_x || !clu_y || !feat) return fail(VELO_ERR_ARG, "null argument");
+    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "normalisation not set (velo_mlp_set_weights)");
+    HIP_OK(launch_features(c->p, c->mlp.d_norm, n, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, feat, feat32,
+                           (hipStream_t)stream));
+    return VELO_OK;
+}
+
+int velo_mlp_forward(velo_ctx* c, int64_t n, const uint16_t* feat, float* logit, void* stream) {
+    if (!c || n < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    if (n == 0) return VELO_OK;
+    if (!feat || !logit) return fail(VELO_ERR_ARG, "null argument");
+    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "weights not set");
+    HIP_OK(launch_mlp_forward(c->mlp, n, feat, logit, (hipStream_t)stream));
+    return VELO_OK;
+}
+
+int velo_mlp_grad(velo_ctx* c, int64_t n, const uint16_t* feat, const uint8_t* label, float* grad, float* loss,
+                  void* stream) {
+    if (!c || n <= 0 || !feat || !label || !grad) return fail(VELO_ERR_ARG, "bad arguments");
+    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "weights not set");
+    HIP_OK(launch_mlp_grad(c->mlp, n, feat, label, grad, loss, (hipStream_t)stream));
+    return VELO_OK;
+}
+
+int velo_mlp_train_step(velo_ctx* c, int64_t n, const uint16_t* feat, const uint8_t* label, float lr, float* loss,
+                        void* stream) {
+    if (!c || n <= 0 || !feat || !label || !(lr >= 0.0f)) return fail(VELO_ERR_ARG, "bad arguments");
+    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "weights not set");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_mlp_grad(c->mlp, n, feat, label, c->mlp.d_grad, loss, s));
+    c->mlp.step += 1;
+    HIP_OK(launch_adam(c->mlp, lr, s));
+    c->mlp.version++;
+    return VELO_OK;
+}
+
+int velo_mlp_set_adam(velo_ctx* c, float beta1, float beta2, float eps) {
+    if (!c || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(VELO_ERR_ARG, "bad Adam parameters");
+    c->mlp.beta1 = beta1;
+    c->mlp.beta2 = beta2;
+    c->mlp.eps = eps;
+    return VELO_OK;
+}
+
+int velo_mlp_get_state(velo_ctx* c, float* h_master, float* h_m, float* h_v, int64_t* h_step) {
+    if (!c || !h_master || !h_m || !h_v || !h_step) return fail(VELO_ERR_ARG, "null argument");
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(h_master, c->mlp.d_master, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(h_m, c->mlp.d_m, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(h_v, c->mlp.d_v, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+    *h_step = c->mlp.step;
+    return VELO_OK;
+}
+
+int velo_mlp_set_state(velo_ctx* c, const float* h_master, const float* h_m, const float* h_v, int64_t step) {
+    if (!c || !h_master || !h_m || !h_v || step < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(c->mlp.d_master, h_master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->mlp.d_m, h_m, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->mlp.d_v, h_v, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    c->mlp.step = step;
+    c->mlp.version++;
+    return VELO_OK;
+}
+
+}  // extern "C"

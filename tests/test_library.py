@@ -1,0 +1,44 @@
+"""CPU checks of the C-ABI library: it loads and exports every declared symbol,
+and host-side argument validation rejects bad calls (no device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "velo.h")
+LIB = os.path.join(ROOT, "paper_2412_05041_amd", "libvelo.so")
+
+
+def declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(velo_[a-z0-9_]+)\s*\(", src)) - {"VELO_STATUS_WORDS"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2412_05041_amd import build
+        build.build()
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings_and_errors(lib):
+    lib.velo_status_string.restype = C.c_char_p
+    lib.velo_last_error.restype = C.c_char_p
+    assert lib.velo_status_string(0) == b"ok"
+    assert lib.velo_status_string(-2).startswith(b"workspace")
+    # null arguments are rejected before any device call
+    assert lib.velo_create(None, None, 0, None) == -1
+    assert b"null" in lib.velo_last_error()
+    assert lib.velo_cluster(None, 1, None, None, None, None, None, None, None, C.c_int64(0), None, None) == -1
+    assert lib.velo_fit(None, C.c_int64(5), None, None, None, None, None, None, None, None) == -1
