@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -105,7 +106,10 @@ def main():
         v.mlp_set_weights(master, norm)
     v.reserve(E, batch.n_pix, batch.n_pix)
     off, ids = velo.to_device(batch)
-    if not args.no_autotune:
+    if args.launch:
+        th, tl = (int(x) for x in args.launch.split(","))
+        v.set_launch(th, tl)
+    elif not args.no_autotune:
         c = v.cluster(off, ids, with_npix=False)
         v.autotune(c["clu_off"], c["clu_x"], c["clu_y"], reps=2)
         del c

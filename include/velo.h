@@ -189,6 +189,10 @@ int velo_features(velo_ctx* ctx, int64_t n_tracks, const int32_t* d_trk_hit_off,
                   const uint32_t* d_trk_planes, const float* d_clu_x, const float* d_clu_y,
                   uint16_t* d_feat, float* d_feat_f32 /* nullable [n][10] raw FP32 */, void* stream);
 
+/* Standardisation alone: d_raw[n][10] FP32 features -> d_feat[n][16] BF16, by
+ * the same rule as velo_features (used to prepare stored training data). */
+int velo_standardize(velo_ctx* ctx, int64_t n, const float* d_raw, uint16_t* d_feat, void* stream);
+
 /* Logits of n feature rows (BF16 MFMA, FP32 accumulation). */
 int velo_mlp_forward(velo_ctx* ctx, int64_t n, const uint16_t* d_feat, float* d_logit, void* stream);
 

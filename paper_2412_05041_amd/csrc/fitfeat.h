@@ -23,40 +23,37 @@ struct FitResult {
     int first, last;
 };
 
-// Gathers the hits of a track (hit indices in plane order, one per set bit of
-// mask) and fits them.
+// Fits the hits of a track: hit_at(k, i) gives the cluster index of the i-th
+// hit (on plane k) in plane order.  Three passes over the plane mask re-read
+// the coordinates instead of staging them in per-lane arrays.
 template <typename HitAt>
 __device__ __forceinline__ FitResult fit_track_hits(HitAt hit_at, uint32_t mask, const float* clu_x,
                                                     const float* clu_y, const float* zp, float sigma) {
-    float x[kPlanes], y[kPlanes], z[kPlanes];
     FitResult f;
-    int n = 0;
-    f.first = -1;
-    f.last = -1;
-#pragma unroll
-    for (int k = 0; k < kPlanes; ++k) {
-        if (mask & (1u << k)) {
-            const int h = hit_at(k, n);
-            x[n] = clu_x[h];
-            y[n] = clu_y[h];
-            z[n] = zp[k];
-            if (f.first < 0) f.first = k;
-            f.last = k;
-            ++n;
-        }
-    }
+    f.first = mask ? __ffs(mask) - 1 : -1;
+    f.last = mask ? 31 - __clz(mask) : -1;
     float sz = 0.0f, sx = 0.0f, sy = 0.0f;
-    for (int i = 0; i < n; ++i) { sz = sz + z[i]; sx = sx + x[i]; sy = sy + y[i]; }
+    int n = 0;
+    for (uint32_t m = mask; m; m &= m - 1, ++n) {
+        const int k = __ffs(m) - 1;
+        const int h = hit_at(k, n);
+        sz = sz + zp[k];
+        sx = sx + clu_x[h];
+        sy = sy + clu_y[h];
+    }
     const float fn = (float)n;
     f.zr = sz / fn;
     f.xr = sx / fn;
     f.yr = sy / fn;
     float szz = 0.0f, szx = 0.0f, szy = 0.0f;
-    for (int i = 0; i < n; ++i) {
-        const float d = z[i] - f.zr;
+    int i = 0;
+    for (uint32_t m = mask; m; m &= m - 1, ++i) {
+        const int k = __ffs(m) - 1;
+        const int h = hit_at(k, i);
+        const float d = zp[k] - f.zr;
         szz = szz + d * d;
-        szx = szx + d * (x[i] - f.xr);
-        szy = szy + d * (y[i] - f.yr);
+        szx = szx + d * (clu_x[h] - f.xr);
+        szy = szy + d * (clu_y[h] - f.yr);
     }
     f.tx = szx / szz;
     f.ty = szy / szz;
@@ -65,16 +62,19 @@ __device__ __forceinline__ FitResult fit_track_hits(HitAt hit_at, uint32_t mask,
     f.mry = 0.0f;
     f.r_first = 0.0f;
     f.r_last = 0.0f;
-    for (int i = 0; i < n; ++i) {
-        const float d = z[i] - f.zr;
-        const float rx = (x[i] - f.xr) - f.tx * d;
-        const float ry = (y[i] - f.yr) - f.ty * d;
+    i = 0;
+    for (uint32_t m = mask; m; m &= m - 1, ++i) {
+        const int k = __ffs(m) - 1;
+        const int h = hit_at(k, i);
+        const float d = zp[k] - f.zr;
+        const float rx = (clu_x[h] - f.xr) - f.tx * d;
+        const float ry = (clu_y[h] - f.yr) - f.ty * d;
         const float rr = rx * rx + ry * ry;
         ss = ss + rr;
         f.mrx = fmaxf(f.mrx, fabsf(rx));
         f.mry = fmaxf(f.mry, fabsf(ry));
         if (i == 0) f.r_first = rr;
-        if (i == n - 1) f.r_last = rr;
+        f.r_last = rr;
     }
     f.chi2 = ss / (sigma * sigma);
     f.n = n;

@@ -33,6 +33,7 @@ hipError_t launch_mlp_accept(const MlpState& m, const FindArgs& a, hipStream_t s
 hipError_t launch_features(const Params& p, const float* norm, int64_t n, const int32_t* trk_hit_off,
                            const int32_t* trk_hit, const uint32_t* trk_planes, const float* clu_x,
                            const float* clu_y, uint16_t* feat, float* feat32, hipStream_t s);
+hipError_t launch_standardize(const float* norm, int64_t n, const float* raw, uint16_t* feat, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpState& m, int64_t n, const uint16_t* feat, float* logit, hipStream_t s);
 hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const uint8_t* label, float* grad,
                            float* loss, hipStream_t s);

@@ -79,6 +79,7 @@ int set_params(velo_ctx* c, const velo_cuts* cu) {
             return fail(VELO_ERR_ARG, "cuts must be finite and >= 0");
     if (cu->max_skip < 0 || cu->max_skip > 24) return fail(VELO_ERR_ARG, "max_skip out of range");
     if (cu->mode != 0 && cu->mode != 1) return fail(VELO_ERR_ARG, "mode must be 0 or 1");
+    if (!(cu->logit_band >= 0.0f)) return fail(VELO_ERR_ARG, "logit_band must be >= 0");
     if (!(cu->sigma > 0.0f)) return fail(VELO_ERR_ARG, "sigma must be > 0");
     Params& p = c->p;
     p.t_max = cu->t_max;
@@ -609,6 +610,15 @@ int velo_features(velo_ctx* c, int64_t n, const int32_t* trk_hit_off, const int3
     if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "normalisation not set (velo_mlp_set_weights)");
     HIP_OK(launch_features(c->p, c->mlp.d_norm, n, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, feat, feat32,
                            (hipStream_t)stream));
+    return VELO_OK;
+}
+
+int velo_standardize(velo_ctx* c, int64_t n, const float* raw, uint16_t* feat, void* stream) {
+    if (!c || n < 0) return fail(VELO_ERR_ARG, "bad arguments");
+    if (n == 0) return VELO_OK;
+    if (!raw || !feat) return fail(VELO_ERR_ARG, "null argument");
+    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "normalisation not set (velo_mlp_set_weights)");
+    HIP_OK(launch_standardize(c->mlp.d_norm, n, raw, feat, (hipStream_t)stream));
     return VELO_OK;
 }
 

@@ -45,7 +45,7 @@ _SIGS = {
     "velo_find_tracks": [C.c_void_p, C.c_int32] + [C.c_void_p] * 9 + [C.c_int64, C.c_int64, C.c_int32,
                                                                         C.c_void_p, C.c_void_p],
     "velo_fit": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
-    "velo_pipeline": [C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_int64] + [C.c_void_p] * 8 +
+    "velo_pipeline": [C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_int64] + [C.c_void_p] * 7 +
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
     "velo_get_launch": [C.c_void_p, C.c_void_p, C.c_void_p],
@@ -55,6 +55,7 @@ _SIGS = {
     "velo_mlp_get_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_features": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
     "velo_mlp_forward": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+    "velo_standardize": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_mlp_grad": [C.c_void_p, C.c_int64] + [C.c_void_p] * 5,
     "velo_mlp_train_step": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
                             C.c_void_p],
@@ -268,6 +269,12 @@ class Velo:
         _check(lib().velo_features(self.h, n_tracks, _ptr(trk_hit_off), _ptr(trk_hit), _ptr(trk_planes), _ptr(clu_x),
                                    _ptr(clu_y), _ptr(feat), _ptr(f32), _stream()))
         return (feat, f32) if raw else feat
+
+    def standardize(self, raw, n=None):
+        n = raw.shape[0] if n is None else n
+        feat = torch.zeros((max(n, 1), 16), dtype=torch.int16, device=self.device)
+        _check(lib().velo_standardize(self.h, n, _ptr(raw), _ptr(feat), _stream()))
+        return feat
 
     def mlp_forward(self, feat, n=None):
         n = feat.shape[0] if n is None else n

@@ -1,0 +1,200 @@
+"""GPU parity of the learned ghost filter (BF16 MFMA kernels) against the oracle.
+
+Tolerances (BF16 re-rounding after differently ordered FP32 sums):
+  logits within 2e-2 * max(1, |z|); decisions equal wherever |oracle logit| > 2e-2;
+  gradients ||g_gpu - g_oracle|| / ||g_oracle|| <= 1e-2 per tensor;
+  features (FP32 and their BF16 standardisation) bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import cuts, np_
+from paper_2412_05041_amd import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SLICES = {"W1": slice(0, 320), "b1": slice(320, 352), "W2": slice(352, 1376), "b2": slice(1376, 1408),
+          "w3": slice(1408, 1440), "b3": slice(1440, 1441)}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def velo_mod():
+    from paper_2412_05041_amd import velo
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return velo
+
+
+def rand_net(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0, scale, 1441).astype(np.float32)
+    norm = np.concatenate([np.zeros(10), np.ones(10)]).astype(np.float32)
+    return w, norm
+
+
+def rand_feat(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, 1, (n, 10)).astype(np.float32)
+    return oracle.standardize(x, np.concatenate([np.zeros(10), np.ones(10)]).astype(np.float32))
+
+
+def ctx(velo_mod, master, norm, cut="default"):
+    v = velo_mod.Velo(gen.plane_z(), cuts(cut))
+    v.mlp_set_weights(master, norm)
+    return v
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 1000, 4099])
+def test_forward_matches_oracle(velo_mod, n):
+    say(f"[mlp] forward n={n}")
+    master, norm = rand_net(11)
+    xb = rand_feat(n, 12)
+    v = ctx(velo_mod, master, norm)
+    d = torch.from_numpy(xb.view(np.int16)).cuda()
+    z = np_(v.mlp_forward(d, n))
+    zo = oracle.mlp_forward(xb, master, round_on=True)
+    assert np.all(np.abs(z - zo) <= 2e-2 * np.maximum(1.0, np.abs(zo))), np.abs(z - zo).max()
+
+
+def test_features_bit_exact_and_standardisation(velo_mod):
+    b = gen.generate(gen.WORKLOADS["nominal"].with_events(20, 31))
+    cut = cuts("ms")
+    c = oracle.cluster(b.pix_off, b.pix_id)
+    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], b.plane_z, cut, emit_rejected=True)
+    rng = np.random.default_rng(3)
+    norm = np.concatenate([rng.normal(0, 1, 10), rng.uniform(0.5, 2, 10)]).astype(np.float32)
+    v = ctx(velo_mod, rand_net(1)[0], norm, "ms")
+    T = len(t["trk_planes"])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    feat, raw = v.features(dev(t["trk_hit_off"]), dev(t["trk_hit"]), dev(t["trk_planes"].view(np.int32)),
+                           dev(c["clu_x"]), dev(c["clu_y"]), T, raw=True)
+    assert np.array_equal(np_(raw, T).view(np.int32), t["trk_feat"].view(np.int32))
+    ref = oracle.standardize(t["trk_feat"], norm)
+    assert np.array_equal(np_(feat, T).view(np.uint16), ref)
+    s = v.standardize(dev(t["trk_feat"]), T)
+    assert np.array_equal(np_(s, T).view(np.uint16), ref)
+
+
+@pytest.mark.parametrize("n", [65536, 10007])
+def test_gradient_matches_oracle_and_is_deterministic(velo_mod, n):
+    say(f"[mlp] gradient n={n}")
+    master, norm = rand_net(21, 0.3)
+    xb = rand_feat(n, 22)
+    lab = (np.random.default_rng(23).random(n) < 0.3).astype(np.uint8)
+    v = ctx(velo_mod, master, norm)
+    d = torch.from_numpy(xb.view(np.int16)).cuda()
+    dl = torch.from_numpy(lab).cuda()
+    g, loss = v.mlp_grad(d, dl, n)
+    g = np_(g).astype(np.float64)
+    g2, loss2 = v.mlp_grad(d, dl, n)
+    assert np.array_equal(np_(g2), g.astype(np.float32)) and float(loss.item()) == float(loss2.item())
+    lo, go = oracle.mlp_loss_grad(lab, master=master, xb=xb, round_on=True)
+    assert abs(float(loss.item()) - lo) <= 1e-3 * max(1.0, abs(lo))
+    for name, sl in SLICES.items():
+        err = np.linalg.norm(g[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        assert err <= 1e-2, (name, err)
+
+
+def test_adam_step_matches_oracle(velo_mod):
+    n = 4096
+    master, norm = rand_net(31, 0.3)
+    xb = rand_feat(n, 32)
+    lab = (np.random.default_rng(33).random(n) < 0.5).astype(np.uint8)
+    v = ctx(velo_mod, master, norm)
+    d = torch.from_numpy(xb.view(np.int16)).cuda()
+    dl = torch.from_numpy(lab).cuda()
+    g, _ = v.mlp_grad(d, dl, n)
+    g = np_(g).astype(np.float64)
+    v.mlp_train_step(d, dl, 1e-3, n=n)
+    w_gpu, m_gpu, v_gpu, step = v.mlp_get_state()
+    w = master.astype(np.float64)
+    m = np.zeros(1441)
+    vv = np.zeros(1441)
+    oracle.adam(w, m, vv, g, 1, lr=1e-3)
+    assert step == 1
+    assert np.allclose(w_gpu, w, rtol=0, atol=2e-6)
+    assert np.allclose(m_gpu, m, rtol=1e-6, atol=1e-12)
+
+
+def test_training_resume_is_bitwise(velo_mod):
+    n = 65536
+    master, norm = rand_net(41, 0.3)
+    xb = rand_feat(n, 42)
+    lab = (np.random.default_rng(43).random(n) < 0.4).astype(np.uint8)
+    d = torch.from_numpy(xb.view(np.int16)).cuda()
+    dl = torch.from_numpy(lab).cuda()
+    a = ctx(velo_mod, master, norm)
+    for _ in range(6):
+        a.mlp_train_step(d, dl, 1e-2, n=n)
+    full = a.mlp_get_state()
+    b = ctx(velo_mod, master, norm)
+    for _ in range(3):
+        b.mlp_train_step(d, dl, 1e-2, n=n)
+    st = b.mlp_get_state()
+    c = ctx(velo_mod, master, norm)
+    c.mlp_set_state(*st)
+    for _ in range(3):
+        c.mlp_train_step(d, dl, 1e-2, n=n)
+    res = c.mlp_get_state()
+    for x, y in zip(full[:3], res[:3]):
+        assert np.array_equal(x, y)
+    assert full[3] == res[3] == 6
+
+
+def test_learned_mode_decisions_match_oracle(velo_mod):
+    b = gen.generate(gen.WORKLOADS["nominal"].with_events(40, 51))
+    master, _ = rand_net(52, 0.5)
+    rng = np.random.default_rng(53)
+    norm = np.concatenate([[50, 8, 0, 0, 5, 5, 5, 5, 0.6, 0.8], [100, 4, 0.1, 0.1, 5, 5, 10, 10, 0.2, 0.2]]).astype(np.float32)
+    cut = dict(cuts("ms"), mode=1, logit_band=0.1)
+    c = oracle.cluster(b.pix_off, b.pix_id)
+    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], b.plane_z, cut, mlp=(master, norm),
+                           emit_rejected=True)
+    v = velo_mod.Velo(b.plane_z, cut)
+    v.mlp_set_weights(master, norm)
+    v.reserve(b.n_events, b.n_pix, b.n_pix)
+    off, ids = velo_mod.to_device(b)
+    gc = v.cluster(off, ids)
+    gt = v.find_tracks(gc["clu_off"], gc["clu_x"], gc["clu_y"], emit_rejected=True)
+    torch.cuda.synchronize()
+    T = len(t["trk_planes"])
+    # the candidates are unique: bit-identical
+    assert np.array_equal(np_(gt["trk_off"]), t["trk_off"])
+    assert np.array_equal(np_(gt["trk_planes"], T, np.uint32), t["trk_planes"])
+    z = np_(gt["trk_logit"], T)
+    zo = t["trk_logit"]
+    assert np.all(np.abs(z - zo) <= 2e-2 * np.maximum(1.0, np.abs(zo)))
+    fl = np_(gt["trk_flags"], T)
+    sure = np.abs(zo) > 0.1 + 2e-2
+    assert np.array_equal(fl[sure] & 0x0f, t["trk_flags"][sure] & 0x0f)
+    flips = int((fl != t["trk_flags"]).sum())
+    say(f"[mlp] decision flips near the band edge: {flips} of {T}")
+    assert (fl & 8).sum() > 0 and ((fl & 8) == 0).sum() > 0
+
+
+def test_learned_mode_infinite_band_equals_plain(velo_mod):
+    b = gen.generate(gen.WORKLOADS["nominal"].with_events(30, 61))
+    master, norm = rand_net(62)
+    base = cuts("ms")
+    outs = []
+    for cut in (base, dict(base, mode=1, logit_band=float("inf"))):
+        v = velo_mod.Velo(b.plane_z, cut)
+        v.mlp_set_weights(master, norm)
+        v.reserve(b.n_events, b.n_pix, b.n_pix)
+        off, ids = velo_mod.to_device(b)
+        bufs = v.pipeline_buffers(b.n_events, b.n_pix)
+        v.pipeline(off, ids, bufs)
+        torch.cuda.synchronize()
+        st = v.read_status(bufs["status"])
+        T = int(st[2])
+        outs.append((np_(bufs["trk_hit"], int(st[3])).copy(), np_(bufs["trk_flags"], T).copy(), st))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.all(outs[1][1] & 4) and outs[1][2][6] > 0

@@ -42,3 +42,22 @@ def test_status_strings_and_errors(lib):
     assert b"null" in lib.velo_last_error()
     assert lib.velo_cluster(None, 1, None, None, None, None, None, None, None, C.c_int64(0), None, None) == -1
     assert lib.velo_fit(None, C.c_int64(5), None, None, None, None, None, None, None, None) == -1
+
+
+def header_arg_counts():
+    src = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(velo_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header():
+    from paper_2412_05041_amd import velo
+    counts = header_arg_counts()
+    for name, args in velo._SIGS.items():
+        assert name in counts, name
+        assert len(args) == counts[name], (name, len(args), counts[name])
+    # every declared entry point has a binding
+    assert set(counts) == set(velo._SIGS), set(counts) ^ set(velo._SIGS)
