@@ -52,6 +52,7 @@ struct Work {
     int32_t* ev_ncand;    // candidates
     int32_t* ev_nout;     // tracks to output
     int32_t* ev_nouthit;  // hits of those tracks
+    int32_t* ev_ncandhit; // hits of all candidates (emit_rejected output)
     int32_t* ev_tbase;    // exclusive scans of ev_nout / ev_nouthit
     int32_t* ev_hbase;
     int32_t* order;       // event processing order (largest first)

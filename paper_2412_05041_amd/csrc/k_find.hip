@@ -550,9 +550,9 @@ __device__ void accept(S& st, const FindArgs& a, int e) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
     const int nt = sc.n_tracks;
-    if (threadIdx.x == 0) { sc.nout = 0; sc.nouthit = 0; }
+    if (threadIdx.x == 0) { sc.nout = 0; sc.nouthit = 0; sc.any = 0; }
     __syncthreads();
-    int my_out = 0, my_hit = 0;
+    int my_out = 0, my_hit = 0, my_all = 0;
     for (int t = threadIdx.x; t < nt; t += kT) {
         const int64_t slot = st.slot0 + t;
         const uint32_t mask = st.tmask(t);
@@ -577,16 +577,19 @@ __device__ void accept(S& st, const FindArgs& a, int e) {
         }
         a.w.cflags[slot] = fl;
         if constexpr (!S::kLarge) a.w.cmask[slot] = mask;
+        my_all += n;
         my_out += (fl & TRK_ACCEPT) ? 1 : 0;
         my_hit += (fl & TRK_ACCEPT) ? n : 0;
     }
     atomicAdd(&sc.nout, my_out);
     atomicAdd(&sc.nouthit, my_hit);
+    atomicAdd(&sc.any, my_all);
     __syncthreads();
     if (threadIdx.x == 0) {
         a.w.ev_ncand[e] = nt;
         a.w.ev_nout[e] = sc.nout;
         a.w.ev_nouthit[e] = sc.nouthit;
+        a.w.ev_ncandhit[e] = sc.any;
     }
 }
 
@@ -621,6 +624,7 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
     a.w.ev_ncand[e] = 0;
     a.w.ev_nout[e] = 0;
     a.w.ev_nouthit[e] = 0;
+    a.w.ev_ncandhit[e] = 0;
     set_event_flag(a.status, e, flag, 1);
 }
 

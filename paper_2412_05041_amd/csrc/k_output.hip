@@ -49,7 +49,8 @@ __global__ __launch_bounds__(1024) void k_order(Work w, int n_events, const int3
 // Block-wide exclusive scan of per-event counts into ev_tbase/ev_hbase; also
 // trk_off and the totals.  Single workgroup of 1024 threads.
 __global__ __launch_bounds__(kScanThreads) void k_scan(Work w, int n_events, int32_t* trk_off,
-                                                       int32_t* trk_hit_off, int64_t trk_cap, int32_t* status) {
+                                                       int32_t* trk_hit_off, int64_t trk_cap, int32_t* status,
+                                                       int emit) {
     __shared__ int64_t s_t[kScanThreads / kWave], s_h[kScanThreads / kWave];
     __shared__ int64_t carry_t, carry_h;
     if (threadIdx.x == 0) { carry_t = 0; carry_h = 0; }
@@ -57,8 +58,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Work w, int n_events, int
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
     for (int base = 0; base < n_events; base += kScanThreads) {
         const int e = base + threadIdx.x;
-        const int vt = e < n_events ? w.ev_nout[e] : 0;
-        const int vh = e < n_events ? w.ev_nouthit[e] : 0;
+        const int vt = e < n_events ? (emit ? w.ev_ncand[e] : w.ev_nout[e]) : 0;
+        const int vh = e < n_events ? (emit ? w.ev_ncandhit[e] : w.ev_nouthit[e]) : 0;
         int tt, th;
         const int et = wave_excl_scan(vt, &tt);
         const int eh = wave_excl_scan(vh, &th);
@@ -178,7 +179,7 @@ hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hip
 
 hipError_t launch_scan(const OutArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a.w, a.n_events, a.trk_off, a.trk_hit_off,
-                       a.trk_cap, a.status);
+                       a.trk_cap, a.status, a.emit_rejected);
     return hipGetLastError();
 }
 

@@ -124,6 +124,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
     w.ev_ncand = carve<int32_t>(cur, E);
     w.ev_nout = carve<int32_t>(cur, E);
     w.ev_nouthit = carve<int32_t>(cur, E);
+    w.ev_ncandhit = carve<int32_t>(cur, E);
     w.ev_tbase = carve<int32_t>(cur, E);
     w.ev_hbase = carve<int32_t>(cur, E);
     w.order = carve<int32_t>(cur, E);
