@@ -148,13 +148,14 @@ def main():
         acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
     v.set_timing(False)
     stages = {k: acc[k] / args.steps for k in acc}
-    dom = max(("cluster", "find_lds", "find_large", "output_fit"), key=lambda k: stages[k])
+    dom = max(("cluster", "find_lds", "find_large", "accept", "output_fit"), key=lambda k: stages[k])
     # algorithmic bytes per launch (minimum traffic the stage must move)
     n_pix = batch.n_pix
     alg = {
         "cluster": 8 * n_pix + 8 * n_clu + 14 * n_clu,    # ids in, labels out, centroids + staging out
         "find_lds": 8 * n_clu + 4 * H + 8 * T,            # hit coordinates in, track hit lists out
         "find_large": 8 * n_clu + 4 * H + 8 * T,
+        "accept": 12 * H + 8 * T,                         # gather candidate hits, write flags
         "output_fit": 12 * H + 40 * T,                    # gather hits, write CSR + 8-float state
     }
     achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9

@@ -161,7 +161,8 @@ int velo_pipeline(velo_ctx* ctx, int32_t n_events, const int32_t* d_pix_off, con
  * graph) with HIP events recorded on `stream` between the stages; after the
  * call velo_last_timing synchronises the stream and returns the durations (ms)
  * of the VELO_N_STAGES stages: reset, cluster+staging, event order, finder
- * (LDS tiles), finder (large events), learned decision, scan, output+fit. */
+ * (LDS tiles), finder (large events), acceptance (+ learned decision), scan,
+ * output+fit. */
 #define VELO_N_STAGES 8
 int velo_set_timing(velo_ctx* ctx, int32_t on);
 int velo_last_timing(velo_ctx* ctx, float* h_ms, int32_t n);

@@ -57,9 +57,8 @@ struct Work {
     int32_t* ev_hbase;
     int32_t* order;       // event processing order (largest first)
     int32_t* large;       // events for the large-event path
-    uint64_t* lookback;   // decoupled look-back words of the cluster kernel
-    int32_t* counters;    // [0] cluster tickets, [1] finder events, [2] #large, [3] large tickets,
-                          // [4] spin timeouts, [5..7] spare
+    int32_t* seg_m;       // clusters per (event, plane) segment
+    int32_t* counters;    // [1] finder events, [2] #large, [3] large tickets, others spare
     // large-event path, per cluster (global cluster index)
     int32_t* g_claim;
     uint64_t* g_slota;
@@ -68,7 +67,11 @@ struct Work {
     float* g_tty;
     float* g_txb;
     float* g_tyb;
-    int32_t* g_tkb;
+    float* g_dtx;         // downstream end of new tracks
+    float* g_dty;
+    float* g_dxb;
+    float* g_dyb;
+    int32_t* g_tkb;       // planes of the two ends (bits 0-7 upstream, 8-15 downstream)
     int32_t* g_twant;
     // large-event seed pool: per block of the large kernel
     float* p_q;

@@ -23,37 +23,49 @@ struct FitResult {
     int first, last;
 };
 
-// Fits the hits of a track: hit_at(k, i) gives the cluster index of the i-th
-// hit (on plane k) in plane order.  Three passes over the plane mask re-read
-// the coordinates instead of staging them in per-lane arrays.
+// Gathers the coordinates of a track's hits into per-plane registers:
+// hit_at(k, i) gives the cluster index of the i-th hit (on plane k).  Fully
+// unrolled over the 26 planes, so the loads are independent and issue together.
 template <typename HitAt>
-__device__ __forceinline__ FitResult fit_track_hits(HitAt hit_at, uint32_t mask, const float* clu_x,
-                                                    const float* clu_y, const float* zp, float sigma) {
+__device__ __forceinline__ void gather_hits(HitAt hit_at, uint32_t mask, const float* clu_x, const float* clu_y,
+                                            float* x, float* y) {
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k) {
+        if (mask & (1u << k)) {
+            const int h = hit_at(k, __popc(mask & ((1u << k) - 1u)));
+            x[k] = clu_x[h];
+            y[k] = clu_y[h];
+        } else {
+            x[k] = 0.0f;
+            y[k] = 0.0f;
+        }
+    }
+}
+
+// Fit of the gathered hits (planes ascending, left folds from 0).
+__device__ __forceinline__ FitResult fit_hits(const float* x, const float* y, uint32_t mask, const float* zp,
+                                              float sigma) {
     FitResult f;
     f.first = mask ? __ffs(mask) - 1 : -1;
     f.last = mask ? 31 - __clz(mask) : -1;
+    const int n = __popc(mask);
     float sz = 0.0f, sx = 0.0f, sy = 0.0f;
-    int n = 0;
-    for (uint32_t m = mask; m; m &= m - 1, ++n) {
-        const int k = __ffs(m) - 1;
-        const int h = hit_at(k, n);
-        sz = sz + zp[k];
-        sx = sx + clu_x[h];
-        sy = sy + clu_y[h];
-    }
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k)
+        if (mask & (1u << k)) { sz = sz + zp[k]; sx = sx + x[k]; sy = sy + y[k]; }
     const float fn = (float)n;
     f.zr = sz / fn;
     f.xr = sx / fn;
     f.yr = sy / fn;
     float szz = 0.0f, szx = 0.0f, szy = 0.0f;
-    int i = 0;
-    for (uint32_t m = mask; m; m &= m - 1, ++i) {
-        const int k = __ffs(m) - 1;
-        const int h = hit_at(k, i);
-        const float d = zp[k] - f.zr;
-        szz = szz + d * d;
-        szx = szx + d * (clu_x[h] - f.xr);
-        szy = szy + d * (clu_y[h] - f.yr);
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k) {
+        if (mask & (1u << k)) {
+            const float d = zp[k] - f.zr;
+            szz = szz + d * d;
+            szx = szx + d * (x[k] - f.xr);
+            szy = szy + d * (y[k] - f.yr);
+        }
     }
     f.tx = szx / szz;
     f.ty = szy / szz;
@@ -62,24 +74,32 @@ __device__ __forceinline__ FitResult fit_track_hits(HitAt hit_at, uint32_t mask,
     f.mry = 0.0f;
     f.r_first = 0.0f;
     f.r_last = 0.0f;
-    i = 0;
-    for (uint32_t m = mask; m; m &= m - 1, ++i) {
-        const int k = __ffs(m) - 1;
-        const int h = hit_at(k, i);
-        const float d = zp[k] - f.zr;
-        const float rx = (clu_x[h] - f.xr) - f.tx * d;
-        const float ry = (clu_y[h] - f.yr) - f.ty * d;
-        const float rr = rx * rx + ry * ry;
-        ss = ss + rr;
-        f.mrx = fmaxf(f.mrx, fabsf(rx));
-        f.mry = fmaxf(f.mry, fabsf(ry));
-        if (i == 0) f.r_first = rr;
-        f.r_last = rr;
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k) {
+        if (mask & (1u << k)) {
+            const float d = zp[k] - f.zr;
+            const float rx = (x[k] - f.xr) - f.tx * d;
+            const float ry = (y[k] - f.yr) - f.ty * d;
+            const float rr = rx * rx + ry * ry;
+            ss = ss + rr;
+            f.mrx = fmaxf(f.mrx, fabsf(rx));
+            f.mry = fmaxf(f.mry, fabsf(ry));
+            if (k == f.first) f.r_first = rr;
+            f.r_last = rr;
+        }
     }
     f.chi2 = ss / (sigma * sigma);
     f.n = n;
     f.ndof = 2 * n - 4;
     return f;
+}
+
+template <typename HitAt>
+__device__ __forceinline__ FitResult fit_track_hits(HitAt hit_at, uint32_t mask, const float* clu_x,
+                                                    const float* clu_y, const float* zp, float sigma) {
+    float x[kPlanes], y[kPlanes];
+    gather_hits(hit_at, mask, clu_x, clu_y, x, y);
+    return fit_hits(x, y, mask, zp, sigma);
 }
 
 __device__ __forceinline__ void raw_features(const FitResult& f, float sigma, float* o) {

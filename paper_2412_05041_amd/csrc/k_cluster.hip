@@ -1,9 +1,10 @@
 // k_cluster.hip -- pixel clustering and azimuth-sorted hit staging.
 //
-// One wave64 workgroup per (event, plane) segment.  Workgroups take segments
-// from a ticket counter in launch order, so the single-pass decoupled look-back
-// that produces the cluster offsets only ever waits on segments that are
-// already running.
+// Three launches, one wave64 workgroup per (event, plane) segment in the first
+// and the last: (1) clustering with segment-local numbering, centroids parked
+// in the per-pixel scratch; (2) exclusive scan of the per-segment cluster
+// counts into the cluster offsets; (3) global numbering, centroid output and,
+// for the fused pipeline, the azimuth-sorted staging of each segment.
 //
 // Clustering = 8-connected components of the fired pixels.  Each pixel unites
 // with its neighbours of smaller id (same row: id-1; previous row: the three
@@ -70,41 +71,6 @@ __device__ __forceinline__ void unite_neighbours(const Id* ids, P* par, int i) {
     for (int j = lower_bound_u32(ids, i, lo); j < i && ids[j] <= hi; ++j) unite(par, i, j);
 }
 
-__device__ __forceinline__ uint64_t lb_load(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back over segments in ticket order: exclusive prefix of
-// `count`.  Lane 0 only.  The wait is bounded: a timeout is counted in
-// counters[4] (a parity failure, never a hang).
-__device__ int64_t lookback(uint64_t* lb, int seg, int64_t count, int32_t* timeouts) {
-    constexpr uint64_t kAgg = 1ull << 62, kInc = 2ull << 62, kVal = (1ull << 62) - 1;
-    if (seg == 0) {
-        lb_store(lb, kInc | (uint64_t)count);
-        return 0;
-    }
-    lb_store(lb + seg, kAgg | (uint64_t)count);
-    int64_t excl = 0;
-    int j = seg - 1;
-    uint32_t spins = 0;
-    while (j >= 0) {
-        const uint64_t v = lb_load(lb + j);
-        const uint64_t f = v >> 62;
-        if (f == 0) {
-            if (++spins > (1u << 24)) { atomicAdd(timeouts, 1); break; }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += (int64_t)(v & kVal);
-        if (f == 2) break;
-        --j;
-    }
-    lb_store(lb + seg, kInc | (uint64_t)(excl + count));
-    return excl;
-}
 
 // Azimuth-sorted staging of the m clusters of one segment, by (key, index).
 // kbuf/tbuf: m-element scratch; hist: nb counters (LDS).  Staged entry g =
@@ -160,18 +126,16 @@ __device__ void stage_segment(const float* cx, const float* cy, int m, int64_t g
     }
 }
 
-// Clustering of one segment.  kSmall: every array in LDS; otherwise the
-// parent/rank/sum arrays live in the per-pixel global scratch.
+// Clustering of one segment with segment-local numbering.  kSmall: parent and
+// rank arrays and the sums in LDS; otherwise in the per-pixel global scratch.
+// Writes pix_clu = local rank, seg_m = cluster count and, at pixel-indexed
+// scratch positions p0 + j, the centroid x, y and pixel count of cluster j.
 template <bool kSmall, typename Id, typename P, typename R>
-__device__ void cluster_segment(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
-                                unsigned long long* s_sum, uint32_t* s_hist, int64_t* s_cbase, int* s_m,
-                                int refuse) {
+__device__ void cluster_local(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
+                              unsigned long long* s_sum, int refuse) {
     const int lane = threadIdx.x;
     const Work& w = a.w;
     const int e = seg / kPlanes;
-
-    // refuse: the segment cannot be clustered (no scratch for it); it then
-    // contributes no clusters and its event is flagged
     int bad = refuse;
     if (a.validate && !refuse) {
         for (int i = lane; i < n; i += kWave) {
@@ -180,52 +144,32 @@ __device__ void cluster_segment(const ClusterArgs& a, int seg, int p0, int n, co
         }
     }
     bad = __syncthreads_or(bad);
-    int m = 0;
-    if (!bad) {
-        for (int i = lane; i < n; i += kWave) par[i] = i;
-        __syncthreads();
-        for (int i = lane; i < n; i += kWave) unite_neighbours(ids, par, i);
-        __syncthreads();
-        for (int i = lane; i < n; i += kWave) rnk[i] = find_root(par, i);
-        __syncthreads();
-        // number the roots in index order; par[root] := its rank
-        for (int c0 = 0; c0 < n; c0 += kWave) {
-            const int i = c0 + lane;
-            const int isroot = (i < n && rnk[i] == i) ? 1 : 0;
-            int tot;
-            const int ex = wave_excl_scan(isroot, &tot);
-            if (isroot) par[i] = m + ex;
-            m += tot;
-        }
-        __syncthreads();
-        for (int i = lane; i < n; i += kWave) rnk[i] = par[rnk[i]];
-    }
-    __syncthreads();
-    if (lane == 0) {
-        const int64_t cb = lookback(w.lookback, seg, m, w.counters + 4);
-        a.clu_off[seg] = (int32_t)cb;
-        if (seg == a.n_seg - 1) {
-            a.clu_off[a.n_seg] = (int32_t)(cb + m);
-            if (a.status) {
-                a.status[ST_NCLU] = (int32_t)(cb + m);
-                a.status[ST_NPIX] = a.pix_off[a.n_seg];
-            }
-        }
-        *s_cbase = cb;
-        *s_m = m;
-    }
-    __syncthreads();
-    const int64_t cbase = *s_cbase;
     if (bad) {
         for (int i = lane; i < n; i += kWave) a.pix_clu[p0 + i] = -1;
-        if (lane == 0) set_event_flag(a.status, e, refuse ? EV_OVERFLOW : EV_BAD_INPUT, refuse ? 1 : 2);
-        *s_m = -1;
+        if (lane == 0) {
+            w.seg_m[seg] = 0;
+            set_event_flag(a.status, e, refuse ? EV_OVERFLOW : EV_BAD_INPUT, refuse ? 1 : 2);
+        }
         return;
     }
-    const bool fits = cbase + m <= a.clu_cap;
-    if (!fits) {
-        if (lane == 0) set_event_flag(a.status, e, EV_OVERFLOW, 1);
+    for (int i = lane; i < n; i += kWave) par[i] = i;
+    __syncthreads();
+    for (int i = lane; i < n; i += kWave) unite_neighbours(ids, par, i);
+    __syncthreads();
+    for (int i = lane; i < n; i += kWave) rnk[i] = find_root(par, i);
+    __syncthreads();
+    // number the roots in index order; par[root] := its rank
+    int m = 0;
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+        const int i = c0 + lane;
+        const int isroot = (i < n && rnk[i] == i) ? 1 : 0;
+        int tot;
+        const int ex = wave_excl_scan(isroot, &tot);
+        if (isroot) par[i] = m + ex;
+        m += tot;
     }
+    __syncthreads();
+    for (int i = lane; i < n; i += kWave) rnk[i] = par[rnk[i]];
     if (kSmall) {
         for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
     } else {
@@ -234,7 +178,7 @@ __device__ void cluster_segment(const ClusterArgs& a, int seg, int p0, int n, co
     __syncthreads();
     for (int i = lane; i < n; i += kWave) {
         const int rk = rnk[i];
-        a.pix_clu[p0 + i] = (int32_t)(cbase + rk);
+        a.pix_clu[p0 + i] = rk;
         const uint32_t id = ids[i];
         const uint32_t c = id % kSide, r = id / kSide;
         if (kSmall) {
@@ -247,66 +191,119 @@ __device__ void cluster_segment(const ClusterArgs& a, int seg, int p0, int n, co
         }
     }
     __syncthreads();
-    if (fits) {
-        for (int j = lane; j < m; j += kWave) {
-            uint32_t sc, sr, cnt;
-            if (kSmall) {
-                const unsigned long long v = s_sum[j];
-                sc = (uint32_t)(v >> 32);
-                cnt = (uint32_t)((v >> 21) & 0x7ffu);
-                sr = (uint32_t)(v & 0x1fffffu);
-            } else {
-                sc = w.g_sc[p0 + j];
-                sr = w.g_sr[p0 + j];
-                cnt = w.g_cnt[p0 + j];
-            }
-            const float fn = (float)cnt;
-            a.clu_x[cbase + j] = ((float)sc / fn - 726.5f) * 0.055f;
-            a.clu_y[cbase + j] = ((float)sr / fn - 726.5f) * 0.055f;
-            if (a.clu_npix) a.clu_npix[cbase + j] = (int32_t)cnt;
+    for (int j = lane; j < m; j += kWave) {
+        uint32_t sc, sr, cnt;
+        if (kSmall) {
+            const unsigned long long v = s_sum[j];
+            sc = (uint32_t)(v >> 32);
+            cnt = (uint32_t)((v >> 21) & 0x7ffu);
+            sr = (uint32_t)(v & 0x1fffffu);
+        } else {
+            sc = w.g_sc[p0 + j];
+            sr = w.g_sr[p0 + j];
+            cnt = w.g_cnt[p0 + j];
         }
-    } else if (lane == 0) {
-        *s_m = -1;  // nothing to stage
+        const float fn = (float)cnt;
+        // centroid parked in the scratch (same slots as the sums: read before write)
+        w.g_sc[p0 + j] = __float_as_uint(((float)sc / fn - 726.5f) * 0.055f);
+        w.g_sr[p0 + j] = __float_as_uint(((float)sr / fn - 726.5f) * 0.055f);
+        w.g_cnt[p0 + j] = cnt;
     }
+    if (lane == 0) w.seg_m[seg] = m;
 }
 
 __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
     __shared__ uint32_t s_id[kCap];
     __shared__ int32_t s_par[kCap];
     __shared__ int32_t s_rnk[kCap];
-    __shared__ unsigned long long s_sum[kCap];  // also the 2048-bucket histogram of large segments
-    __shared__ uint32_t s_hist[kSmallBuckets];
-    __shared__ int64_t s_cbase;
-    __shared__ int s_seg, s_m;
-    static_assert(sizeof(s_sum) >= kBuckets * sizeof(uint32_t), "histogram overlay");
-    const Work& w = a.w;
-    if (threadIdx.x == 0) s_seg = atomicAdd(w.counters + 0, 1);
-    __syncthreads();
-    const int seg = s_seg;
+    __shared__ unsigned long long s_sum[kCap];
+    const int seg = blockIdx.x;
     if (seg >= a.n_seg) return;
+    const Work& w = a.w;
     const int p0 = a.pix_off[seg];
     const int n = a.pix_off[seg + 1] - p0;
-    const bool small = n <= kCap;
-    if (small) {
+    // the per-pixel scratch covers pixel positions below its capacity
+    const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
+    if (n <= kCap && !refuse) {
         for (int i = threadIdx.x; i < n; i += kWave) s_id[i] = a.pix_id[p0 + i];
         __syncthreads();
-        cluster_segment<true>(a, seg, p0, n, s_id, s_par, s_rnk, s_sum, s_hist, &s_cbase, &s_m, 0);
+        cluster_local<true>(a, seg, p0, n, s_id, s_par, s_rnk, s_sum, 0);
     } else {
-        // the per-pixel scratch covers pixel positions below its capacity
-        const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
-        cluster_segment<false>(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, s_sum, s_hist,
-                               &s_cbase, &s_m, refuse);
+        cluster_local<false>(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, s_sum, refuse);
+    }
+}
+
+// Exclusive scan of the segment cluster counts -> clu_off (single workgroup).
+__global__ __launch_bounds__(1024) void k_scan_seg(ClusterArgs a) {
+    __shared__ int64_t s_w[1024 / kWave];
+    __shared__ int64_t s_carry;
+    const Work& w = a.w;
+    const int n = a.n_seg;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    // each thread scans a contiguous chunk
+    const int per = (n + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    int64_t loc = 0;
+    for (int i = b0; i < b0 + per && i < n; ++i) loc += w.seg_m[i];
+    int tot;
+    // 64-bit chunk sums are small (< 2^31 clusters in a batch): scan them as int
+    const int ex = wave_excl_scan((int)loc, &tot);
+    if (lane == 0) s_w[wid] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t c = 0;
+        for (int i = 0; i < 1024 / kWave; ++i) { const int64_t t = s_w[i]; s_w[i] = c; c += t; }
+        s_carry = c;
+    }
+    __syncthreads();
+    int64_t run = s_w[wid] + ex;
+    for (int i = b0; i < b0 + per && i < n; ++i) {
+        a.clu_off[i] = (int32_t)run;
+        run += w.seg_m[i];
+    }
+    if (threadIdx.x == 0) {
+        a.clu_off[n] = (int32_t)s_carry;
+        if (a.status) {
+            a.status[ST_NCLU] = (int32_t)s_carry;
+            a.status[ST_NPIX] = a.pix_off[n];
+        }
+    }
+}
+
+// Global numbering, centroid output and (fused pipeline) staging.
+__global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
+    __shared__ uint32_t s_k[kCap];
+    __shared__ int32_t s_t[kCap];
+    __shared__ uint32_t s_hist[kBuckets];
+    const int seg = blockIdx.x;
+    if (seg >= a.n_seg) return;
+    const Work& w = a.w;
+    const int p0 = a.pix_off[seg];
+    const int n = a.pix_off[seg + 1] - p0;
+    const int64_t cb = a.clu_off[seg];
+    const int m = a.clu_off[seg + 1] - (int)cb;
+    if ((int64_t)p0 + n > w.cap_scratch) return;  // refused in the first pass
+    for (int i = threadIdx.x; i < n; i += kWave) {
+        const int32_t v = a.pix_clu[p0 + i];
+        if (v >= 0) a.pix_clu[p0 + i] = (int32_t)(cb + v);
+    }
+    if (m <= 0) return;
+    if (cb + m > a.clu_cap) {
+        if (threadIdx.x == 0) set_event_flag(a.status, seg / kPlanes, EV_OVERFLOW, 1);
+        return;
+    }
+    const float* tx = reinterpret_cast<const float*>(w.g_sc + p0);
+    const float* ty = reinterpret_cast<const float*>(w.g_sr + p0);
+    for (int j = threadIdx.x; j < m; j += kWave) {
+        a.clu_x[cb + j] = tx[j];
+        a.clu_y[cb + j] = ty[j];
+        if (a.clu_npix) a.clu_npix[cb + j] = (int32_t)w.g_cnt[p0 + j];
     }
     if (!a.stage) return;
-    __syncthreads();
-    const int m = s_m;
-    if (m <= 0) return;
-    const int64_t cb = s_cbase;
     if (m <= kCap) {
-        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_id, s_rnk, s_hist, w);
+        stage_segment<kSmallBuckets>(tx, ty, m, cb, s_k, s_t, s_hist, w);
     } else {
-        stage_segment<kBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0,
-                                (uint32_t*)s_sum, w);
+        stage_segment<kBuckets>(tx, ty, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0, s_hist, w);
     }
 }
 
@@ -333,6 +330,12 @@ __global__ __launch_bounds__(kWave) void k_stage(StageArgs a) {
 hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s) {
     if (a.n_seg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cluster, dim3(a.n_seg), dim3(kWave), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_seg, dim3(1), dim3(1024), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cluster_final, dim3(a.n_seg), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 

@@ -15,15 +15,18 @@
 //       consecutive indices in that order.
 //   T3  the new tracks are extended downstream (planes k+3 .. 25) in lockstep,
 //       with the same rule as T1.
-// After the last plane every track is fitted (least squares, FP32) and
-// accepted when chi2/ndof <= c3 (3 hits) or c4.  Every expression follows the
-// oracle's order of operations; the device code is built without contraction.
+// A separate kernel then fits every candidate (least squares, FP32) and accepts
+// it when chi2/ndof <= c3 (3 hits) or c4 (plain mode), or writes its features
+// for the learned decision.  Every expression follows the oracle's order of
+// operations; the device code is built without contraction.
 //
 // Parallel formulation (identical results):
 //   * hits of each plane are staged sorted by azimuth; a candidate search only
 //     visits hits whose azimuth lies in a window that provably contains every
 //     hit passing the exact cut (plus a margin far above rounding), and the
 //     exact FP32 cut then decides;
+//   * the planes k .. k+4 sit in an LDS ring, which covers seeding (k .. k+2)
+//     and the usual reach of the downstream completion (k+3, k+4);
 //   * T1/T3 conflicts: atomicMin of the track index on the wanted hit;
 //   * T2 greedy: rounds of "every candidate that holds the smallest key on all
 //     three of its hits wins" (two-phase 64/32-bit atomicMin on (q, h0) then
@@ -39,6 +42,7 @@ namespace {
 constexpr float kPi = 3.14159265358979f;
 constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kIntMax = 0x7fffffff;
+constexpr int kRing = 5;  // planes k .. k+4 in the window
 
 // ---------------------------------------------------------------- storage
 // Accessors hide where a workgroup keeps its per-event state: the LDS tile
@@ -46,30 +50,31 @@ constexpr int kIntMax = 0x7fffffff;
 
 template <int kP, int kT, int kC>
 struct Tile {
-    float wx[3][kP];
-    float wy[3][kP];
-    int32_t wid[3][kP];
-    uint64_t slota[3][kP];
+    float wx[kRing][kP];
+    float wy[kRing][kP];
+    uint64_t slota[3][kP];  // seeding planes k, k+1, k+2
     uint32_t slotb[3][kP];
     int32_t claim[kP];
     int32_t claimT[kP];
-    uint16_t wk[3][kP];
-    uint8_t wu[3][kP];
+    uint16_t wid[kRing][kP];  // plane-local cluster index
+    uint16_t wk[kRing][kP];
+    uint8_t wu[kRing][kP];
+    // tracks: upstream end (T1) and downstream end (T3)
     float ttx[kT], tty[kT], txb[kT], tyb[kT];
+    float dtx[kT], dty[kT], dxb[kT], dyb[kT];
     uint32_t tmask[kT];
     int32_t twant[kT];
-    int8_t tkb[kT];
+    int8_t tkb[kT], dkb[kT];
     float cq[kC];
     uint16_t cp[kC][3];
     uint8_t calive[kC];
 };
 
 struct Scalars {
-    int n_tracks, n_cand, n_acc, abort, any, event, nout, nouthit;
-    int wn[3];
-    int64_t wg[3];
-    int64_t cb[kPlanes + 1];  // global cluster offsets of the event's planes
-    uint32_t hist[256];
+    int n_tracks, n_cand, n_acc, event;
+    int wn[kRing];
+    int64_t wg[kRing];       // staged (= cluster) base of the plane in each ring slot
+    int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
 };
 
 template <int kP, int kT, int kC>
@@ -77,34 +82,42 @@ struct LdsStore {
     static constexpr bool kLarge = false;
     Tile<kP, kT, kC>* t;
     Scalars* s;
-    const Work* w;
     int64_t slot0;
+    int seed_k = 0;
     __device__ float X(int sl, int i) const { return t->wx[sl][i]; }
     __device__ float Y(int sl, int i) const { return t->wy[sl][i]; }
     __device__ int K(int sl, int i) const { return t->wk[sl][i]; }
-    __device__ int ID(int sl, int i) const { return t->wid[sl][i]; }
+    __device__ int L(int sl, int i) const { return t->wid[sl][i]; }  // plane-local index
+    __device__ int64_t ID(int sl, int i) const { return s->wg[sl] + t->wid[sl][i]; }
     __device__ uint8_t& U(int sl, int i) { return t->wu[sl][i]; }
-    __device__ int32_t* claim(int sl) { return t->claim; }
+    __device__ int32_t* claim(int) { return t->claim; }
     __device__ int32_t* claimT(int64_t) { return t->claimT; }
-    __device__ uint64_t* slotA(int sl) { return t->slota[sl]; }
-    __device__ uint32_t* slotB(int sl) { return t->slotb[sl]; }
+    __device__ uint64_t* slotA(int role) { return t->slota[role]; }
+    __device__ uint32_t* slotB(int role) { return t->slotb[role]; }
     __device__ float& ttx(int i) { return t->ttx[i]; }
     __device__ float& tty(int i) { return t->tty[i]; }
     __device__ float& txb(int i) { return t->txb[i]; }
     __device__ float& tyb(int i) { return t->tyb[i]; }
+    __device__ float& dtx(int i) { return t->dtx[i]; }
+    __device__ float& dty(int i) { return t->dty[i]; }
+    __device__ float& dxb(int i) { return t->dxb[i]; }
+    __device__ float& dyb(int i) { return t->dyb[i]; }
     __device__ int tkb(int i) const { return t->tkb[i]; }
     __device__ void set_tkb(int i, int v) { t->tkb[i] = (int8_t)v; }
+    __device__ int dkb(int i) const { return t->dkb[i]; }
+    __device__ void set_dkb(int i, int v) { t->dkb[i] = (int8_t)v; }
     __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
     __device__ int32_t& twant(int i) { return t->twant[i]; }
     __device__ float& cq(int i) { return t->cq[i]; }
     __device__ int cp(int i, int j) const { return t->cp[i][j]; }
-    __device__ void set_cp(int i, int a, int b, int c) { t->cp[i][0] = (uint16_t)a; t->cp[i][1] = (uint16_t)b; t->cp[i][2] = (uint16_t)c; }
+    __device__ void set_cp(int i, int a, int b, int c) {
+        t->cp[i][0] = (uint16_t)a; t->cp[i][1] = (uint16_t)b; t->cp[i][2] = (uint16_t)c;
+    }
     __device__ uint8_t& calive(int i) { return t->calive[i]; }
     __device__ uint64_t* wkey64() { return &t->slota[0][0]; }  // winner keys (after the rounds)
     __device__ uint32_t* wtmp() { return &t->slotb[0][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
-    __device__ int cap_plane() const { return kP; }
 };
 
 struct GlobalStore {
@@ -114,21 +127,29 @@ struct GlobalStore {
     int64_t slot0;   // first candidate slot of the event
     int64_t pool0;   // first seed-pool entry of this workgroup
     int cap_t;
+    int seed_k = 0;  // plane of h0 during seeding
     __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
     __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
     __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
-    __device__ int ID(int sl, int i) const { return w->sid[s->wg[sl] + i]; }
+    __device__ int L(int sl, int i) const { return (int)(w->sid[s->wg[sl] + i] - s->wg[sl]); }
+    __device__ int64_t ID(int sl, int i) const { return w->sid[s->wg[sl] + i]; }
     __device__ uint8_t& U(int sl, int i) { return w->used[s->wg[sl] + i]; }
     __device__ int32_t* claim(int sl) { return w->g_claim + s->wg[sl]; }
     __device__ int32_t* claimT(int64_t g) { return w->g_claim + g; }
-    __device__ uint64_t* slotA(int sl) { return w->g_slota + s->wg[sl]; }
-    __device__ uint32_t* slotB(int sl) { return w->g_slotb + s->wg[sl]; }
+    __device__ uint64_t* slotA(int role) { return w->g_slota + s->cb[seed_k + role]; }
+    __device__ uint32_t* slotB(int role) { return w->g_slotb + s->cb[seed_k + role]; }
     __device__ float& ttx(int i) { return w->g_ttx[slot0 + i]; }
     __device__ float& tty(int i) { return w->g_tty[slot0 + i]; }
     __device__ float& txb(int i) { return w->g_txb[slot0 + i]; }
     __device__ float& tyb(int i) { return w->g_tyb[slot0 + i]; }
-    __device__ int tkb(int i) const { return w->g_tkb[slot0 + i]; }
-    __device__ void set_tkb(int i, int v) { w->g_tkb[slot0 + i] = v; }
+    __device__ float& dtx(int i) { return w->g_dtx[slot0 + i]; }
+    __device__ float& dty(int i) { return w->g_dty[slot0 + i]; }
+    __device__ float& dxb(int i) { return w->g_dxb[slot0 + i]; }
+    __device__ float& dyb(int i) { return w->g_dyb[slot0 + i]; }
+    __device__ int tkb(int i) const { return w->g_tkb[slot0 + i] & 0xff; }
+    __device__ void set_tkb(int i, int v) { w->g_tkb[slot0 + i] = (w->g_tkb[slot0 + i] & ~0xff) | v; }
+    __device__ int dkb(int i) const { return (w->g_tkb[slot0 + i] >> 8) & 0xff; }
+    __device__ void set_dkb(int i, int v) { w->g_tkb[slot0 + i] = (w->g_tkb[slot0 + i] & ~0xff00) | (v << 8); }
     __device__ uint32_t& tmask(int i) { return w->cmask[slot0 + i]; }
     __device__ int32_t& twant(int i) { return w->g_twant[slot0 + i]; }
     __device__ float& cq(int i) { return w->p_q[pool0 + i]; }
@@ -138,11 +159,10 @@ struct GlobalStore {
         h[0] = a; h[1] = b; h[2] = c;
     }
     __device__ uint8_t& calive(int i) { return w->p_alive[pool0 + i]; }
-    __device__ uint64_t* wkey64() { return w->g_slota + s->wg[0]; }
-    __device__ uint32_t* wtmp() { return w->g_slotb + s->wg[0]; }
+    __device__ uint64_t* wkey64() { return w->g_slota + s->cb[seed_k]; }
+    __device__ uint32_t* wtmp() { return w->g_slotb + s->cb[seed_k]; }
     __device__ int cap_tracks() const { return cap_t; }
     __device__ int cap_cand() const { return (int)w->pool_cap; }
-    __device__ int cap_plane() const { return 65535; }
 };
 
 // ---------------------------------------------------------------- windows
@@ -191,15 +211,35 @@ __device__ __forceinline__ void visit(KF key, int n, int nr, const int* lo, cons
     }
 }
 
+// Best unused hit (q, index) within e_max of (ex, ey) on a staged plane.
+template <class KF, class UF, class XF, class YF, class IF>
+__device__ __forceinline__ int best_hit(KF key, UF used, XF xf, YF yf, IF idf, int n, float ex, float ey,
+                                        const Params& p) {
+    int lo[2], hi[2];
+    const int nr = point_window(ex, ey, p.r_ext, lo, hi);
+    float bq = 0.0f;
+    int bid = kIntMax, want = -1;
+    visit(key, n, nr, lo, hi, [&](int i) {
+        if (used(i)) return;
+        const float dx = xf(i) - ex;
+        const float dy = yf(i) - ey;
+        const float q = dx * dx + dy * dy;
+        if (!(q <= p.e_max)) return;
+        const int id = idf(i);
+        if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+    });
+    return want;
+}
+
 // ---------------------------------------------------------------- steps
 
 template <int kT, class S>
 __device__ void load_plane(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
-    const int sl = k % 3;
+    const int sl = k % kRing;
     if constexpr (!S::kLarge) {
         // hand the used flags of the plane leaving this slot back to global memory
-        if (k + 3 < kPlanes) {
+        if (k + kRing < kPlanes) {
             const int64_t g = sc.wg[sl];
             for (int i = threadIdx.x; i < sc.wn[sl]; i += kT) a.w.used[g + i] = st.U(sl, i);
         }
@@ -210,32 +250,31 @@ __device__ void load_plane(S& st, const FindArgs& a, int k) {
         sc.wn[sl] = (int)(sc.cb[k + 1] - sc.cb[k]);
     }
     __syncthreads();
-    const int n = sc.wn[sl];
-    const int64_t g = sc.wg[sl];
     if constexpr (!S::kLarge) {
+        const int n = sc.wn[sl];
+        const int64_t g = sc.wg[sl];
         auto* t = st.t;
         for (int i = threadIdx.x; i < n; i += kT) {
             t->wx[sl][i] = a.w.sx[g + i];
             t->wy[sl][i] = a.w.sy[g + i];
             t->wk[sl][i] = a.w.skey[g + i];
-            t->wid[sl][i] = a.w.sid[g + i];
+            t->wid[sl][i] = (uint16_t)(a.w.sid[g + i] - g);
             t->wu[sl][i] = 0;
             t->claim[i] = kIntMax;
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // T1: extend open tracks onto plane k.
 template <int kT, class S>
 __device__ void forward(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
-    const int sl = k % 3;
+    const int sl = k % kRing;
     const int n = sc.wn[sl];
     const int nt = sc.n_tracks;
     const Params& p = a.p;
     int32_t* claim = st.claim(sl);
-    auto key = [&](int i) { return st.K(sl, i); };
     for (int t = threadIdx.x; t < nt; t += kT) {
         int want = -1;
         const int kb = st.tkb(t);
@@ -243,19 +282,9 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             const float d = p.z[k] - p.z[kb];
             const float ex = st.txb(t) + st.ttx(t) * d;
             const float ey = st.tyb(t) + st.tty(t) * d;
-            int lo[2], hi[2];
-            const int nr = point_window(ex, ey, p.r_ext, lo, hi);
-            float bq = 0.0f;
-            int bid = kIntMax;
-            visit(key, n, nr, lo, hi, [&](int i) {
-                if (st.U(sl, i)) return;
-                const float dx = st.X(sl, i) - ex;
-                const float dy = st.Y(sl, i) - ey;
-                const float q = dx * dx + dy * dy;
-                if (!(q <= p.e_max)) return;
-                const int id = st.ID(sl, i);
-                if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
-            });
+            want = best_hit([&](int i) { return st.K(sl, i); }, [&](int i) { return st.U(sl, i); },
+                            [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
+                            [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
             if (want >= 0) atomicMin(claim + want, t);
         }
         st.twant(t) = want;
@@ -265,7 +294,6 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
         const int i = st.twant(t);
         if (i >= 0 && claim[i] == t) {
             st.U(sl, i) = 1;
-            const int id = st.ID(sl, i);
             const float xh = st.X(sl, i), yh = st.Y(sl, i);
             const int kb = st.tkb(t);
             const float dz = p.z[kb] - p.z[k];
@@ -275,7 +303,7 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             st.tyb(t) = yh;
             st.set_tkb(t, k);
             st.tmask(t) |= 1u << k;
-            a.w.chits[(st.slot0 + t) * kPlanes + k] = id;
+            a.w.chits[(st.slot0 + t) * kPlanes + k] = (int32_t)st.ID(sl, i);
         }
     }
     __syncthreads();
@@ -291,7 +319,7 @@ template <int kT, class S>
 __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
-    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const int n0 = sc.wn[s0], n1 = sc.wn[s1], n2 = sc.wn[s2];
     if (threadIdx.x == 0) sc.n_cand = 0;
     __syncthreads();
@@ -343,31 +371,36 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     return sc.n_cand <= cap;
 }
 
-// T2 greedy claiming by rounds of local minima; fills acc[] with the winners.
+// T2 greedy claiming by rounds of local minima; winners end marked 3.
+// Candidate states: 1 alive, 2 won this round, 3 settled winner, 0 dead.
 template <int kT, class S>
 __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
-    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const int nc = sc.n_cand;
-    const int64_t b0 = sc.cb[k], b1 = sc.cb[k + 1], b2 = sc.cb[k + 2];
-    uint64_t* A0 = st.slotA(s0);
-    uint64_t* A1 = st.slotA(s1);
-    uint64_t* A2 = st.slotA(s2);
-    uint32_t* B0 = st.slotB(s0);
-    uint32_t* B1 = st.slotB(s1);
-    uint32_t* B2 = st.slotB(s2);
-    for (int sl = 0; sl < 3; ++sl) {
-        uint64_t* A = st.slotA(sl);
-        uint32_t* B = st.slotB(sl);
-        for (int i = threadIdx.x; i < sc.wn[sl]; i += kT) { A[i] = ~0ull; B[i] = ~0u; }
+    uint64_t* A0 = st.slotA(0);
+    uint64_t* A1 = st.slotA(1);
+    uint64_t* A2 = st.slotA(2);
+    uint32_t* B0 = st.slotB(0);
+    uint32_t* B1 = st.slotB(1);
+    uint32_t* B2 = st.slotB(2);
+    const int nr[3] = {sc.wn[s0], sc.wn[s1], sc.wn[s2]};
+    for (int r = 0; r < 3; ++r) {
+        uint64_t* A = st.slotA(r);
+        uint32_t* B = st.slotB(r);
+        for (int i = threadIdx.x; i < nr[r]; i += kT) { A[i] = ~0ull; B[i] = ~0u; }
     }
-    if (threadIdx.x == 0) sc.n_acc = 0;
     __syncthreads();
+    auto keyA = [&](int c) {
+        return ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
+    };
+    auto keyB = [&](int c) {
+        return ((uint32_t)st.L(s1, st.cp(c, 1)) << 16) | (uint32_t)st.L(s2, st.cp(c, 2));
+    };
     while (true) {
         for (int c = threadIdx.x; c < nc; c += kT) {
             if (st.calive(c) != 1) continue;
-            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) |
-                                (uint32_t)(st.ID(s0, st.cp(c, 0)) - b0);
+            const uint64_t kA = keyA(c);
             atomicMin((unsigned long long*)(A0 + st.cp(c, 0)), kA);
             atomicMin((unsigned long long*)(A1 + st.cp(c, 1)), kA);
             atomicMin((unsigned long long*)(A2 + st.cp(c, 2)), kA);
@@ -376,9 +409,9 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
         for (int c = threadIdx.x; c < nc; c += kT) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
-            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, i0) - b0);
+            const uint64_t kA = keyA(c);
             if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA) {
-                const uint32_t kB = ((uint32_t)(st.ID(s1, i1) - b1) << 16) | (uint32_t)(st.ID(s2, i2) - b2);
+                const uint32_t kB = keyB(c);
                 atomicMin(B0 + i0, kB);
                 atomicMin(B1 + i1, kB);
                 atomicMin(B2 + i2, kB);
@@ -388,10 +421,10 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
         for (int c = threadIdx.x; c < nc; c += kT) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
-            const uint64_t kA = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, i0) - b0);
-            const uint32_t kB = ((uint32_t)(st.ID(s1, i1) - b1) << 16) | (uint32_t)(st.ID(s2, i2) - b2);
+            const uint64_t kA = keyA(c);
+            const uint32_t kB = keyB(c);
             if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA && B0[i0] == kB && B1[i1] == kB && B2[i2] == kB) {
-                st.calive(c) = 2;  // winner
+                st.calive(c) = 2;
                 st.U(s0, i0) = 1;
                 st.U(s1, i1) = 1;
                 st.U(s2, i2) = 1;
@@ -401,12 +434,12 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
         int any = 0;
         for (int c = threadIdx.x; c < nc; c += kT) {
             const uint8_t al = st.calive(c);
-            if (al != 1 && al != 2) continue;  // dead, or a winner of an earlier round
+            if (al != 1 && al != 2) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             A0[i0] = ~0ull; A1[i1] = ~0ull; A2[i2] = ~0ull;
             B0[i0] = ~0u; B1[i1] = ~0u; B2[i2] = ~0u;
             if (al == 2) {
-                st.calive(c) = 3;  // settled winner
+                st.calive(c) = 3;
             } else if (st.U(s0, i0) || st.U(s1, i1) || st.U(s2, i2)) {
                 st.calive(c) = 0;
             } else {
@@ -417,16 +450,69 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
     }
 }
 
+// One downstream completion step (plane j) of the tracks [t0, t1).  The plane
+// is read through the accessors given (LDS ring or global staging).  Returns
+// (uniformly) whether any track was still open.
+template <int kT, class S, class KF, class UF, class XF, class YF, class IF>
+__device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, KF key,
+                               UF used, XF xf, YF yf, IF idf, int64_t gbase) {
+    const Params& p = a.p;
+    if constexpr (!S::kLarge) {
+        for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
+        __syncthreads();
+    }
+    int active = 0;
+    for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+        int want = -1;
+        const int kb = st.dkb(t);
+        if (j - kb - 1 <= p.max_skip) {
+            active = 1;
+            const float d = p.z[j] - p.z[kb];
+            const float ex = st.dxb(t) + st.dtx(t) * d;
+            const float ey = st.dyb(t) + st.dty(t) * d;
+            if (n > 0) {
+                want = best_hit(key, used, xf, yf, idf, n, ex, ey, p);
+                if (want >= 0) atomicMin(claimT + want, t);
+            }
+        }
+        st.twant(t) = want;
+    }
+    if (!__syncthreads_or(active)) return false;
+    for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+        const int i = st.twant(t);
+        if (i >= 0 && claimT[i] == t) {
+            used(i) = 1;
+            const float xh = xf(i), yh = yf(i);
+            const int kb = st.dkb(t);
+            const float dz = p.z[kb] - p.z[j];
+            st.dtx(t) = (st.dxb(t) - xh) / dz;
+            st.dty(t) = (st.dyb(t) - yh) / dz;
+            st.dxb(t) = xh;
+            st.dyb(t) = yh;
+            st.set_dkb(t, j);
+            st.tmask(t) |= 1u << j;
+            a.w.chits[(st.slot0 + t) * kPlanes + j] = (int32_t)(gbase + idf(i));
+        }
+    }
+    __syncthreads();
+    if constexpr (S::kLarge) {
+        for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+            const int i = st.twant(t);
+            if (i >= 0) claimT[i] = kIntMax;
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
 // Rank the winners by (q, h0) -- unique among winners since they share no hit --
-// and create their tracks; then T3.  Returns false on track-capacity overflow.
+// create their tracks, then T3.  Returns false on track-capacity overflow.
 template <int kT, class S>
 __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
-    const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
-    const int64_t b0 = sc.cb[k];
+    const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const int t0 = sc.n_tracks;
-    // collect the winners (candidates marked 3)
     uint64_t* wkey = st.wkey64();
     uint32_t* wc = st.wtmp();
     if (threadIdx.x == 0) sc.n_acc = 0;
@@ -443,11 +529,9 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     if (nw == 0) return true;
     for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
-        wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)(st.ID(s0, st.cp(c, 0)) - b0);
+        wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
     }
     __syncthreads();
-    // rank by counting (winners per step are few in normal events; the large
-    // path pays O(nw^2 / threads), bounded by the plane size)
     for (int i = threadIdx.x; i < nw; i += kT) {
         const uint64_t ki = wkey[i];
         int r = 0;
@@ -457,18 +541,26 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
         const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
         const float x1 = st.X(s1, i1), y1 = st.Y(s1, i1);
+        const float x2 = st.X(s2, i2), y2 = st.Y(s2, i2);
         // upstream end: b = h0 (plane k), a = h1 (plane k+1)
-        const float dz = p.z[k + 1] - p.z[k];
-        st.ttx(t) = (x1 - x0) / dz;
-        st.tty(t) = (y1 - y0) / dz;
+        const float dzu = p.z[k + 1] - p.z[k];
+        st.ttx(t) = (x1 - x0) / dzu;
+        st.tty(t) = (y1 - y0) / dzu;
         st.txb(t) = x0;
         st.tyb(t) = y0;
         st.set_tkb(t, k);
+        // downstream end: b = h2 (plane k+2), a = h1 (plane k+1)
+        const float dzd = p.z[k + 1] - p.z[k + 2];
+        st.dtx(t) = (x1 - x2) / dzd;
+        st.dty(t) = (y1 - y2) / dzd;
+        st.dxb(t) = x2;
+        st.dyb(t) = y2;
+        st.set_dkb(t, k + 2);
         st.tmask(t) = 7u << k;
         int32_t* ch = a.w.chits + (st.slot0 + t) * kPlanes;
-        ch[k] = st.ID(s0, i0);
-        ch[k + 1] = st.ID(s1, i1);
-        ch[k + 2] = st.ID(s2, i2);
+        ch[k] = (int32_t)st.ID(s0, i0);
+        ch[k + 1] = (int32_t)st.ID(s1, i1);
+        ch[k + 2] = (int32_t)st.ID(s2, i2);
     }
     __syncthreads();
     if (threadIdx.x == 0) sc.n_tracks = t0 + nw;
@@ -476,132 +568,36 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
 
     // T3: downstream completion of tracks [t0, t0 + nw), planes k+3 .. 25
     for (int j = k + 3; j < kPlanes; ++j) {
-        const int64_t g = sc.cb[j];
-        const int n = (int)(sc.cb[j + 1] - g);
-        int32_t* claimT = st.claimT(g);
-        if constexpr (!S::kLarge) {
-            for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
-            __syncthreads();
+        bool open;
+        if (!S::kLarge && j < k + kRing) {
+            const int sl = j % kRing;
+            open = complete_plane<kT>(st, a, j, t0, t0 + nw, sc.wn[sl], st.claimT(0),
+                                      [&](int i) { return st.K(sl, i); },
+                                      [&](int i) -> uint8_t& { return st.U(sl, i); },
+                                      [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
+                                      [&](int i) { return st.L(sl, i); }, sc.wg[sl]);
+        } else {
+            const int64_t g = sc.cb[j];
+            const Work& w = a.w;
+            open = complete_plane<kT>(st, a, j, t0, t0 + nw, (int)(sc.cb[j + 1] - g), st.claimT(g),
+                                      [&](int i) { return (int)w.skey[g + i]; },
+                                      [&](int i) -> uint8_t& { return w.used[g + i]; },
+                                      [&](int i) { return w.sx[g + i]; }, [&](int i) { return w.sy[g + i]; },
+                                      [&](int i) { return (int)(w.sid[g + i] - g); }, g);
         }
-        int active = 0;
-        for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
-            int want = -1;
-            const uint32_t m = st.tmask(t);
-            const int kb = 31 - __clz(m);
-            if (j - kb - 1 <= p.max_skip) {
-                active = 1;
-                const int ka = 31 - __clz(m & ~(1u << kb));
-                const int32_t* ch = a.w.chits + (st.slot0 + t) * kPlanes;
-                const float xa = a.clu_x[ch[ka]], ya = a.clu_y[ch[ka]];
-                const float xb = a.clu_x[ch[kb]], yb = a.clu_y[ch[kb]];
-                const float dzab = p.z[ka] - p.z[kb];
-                const float tx = (xa - xb) / dzab;
-                const float ty = (ya - yb) / dzab;
-                const float d = p.z[j] - p.z[kb];
-                const float ex = xb + tx * d;
-                const float ey = yb + ty * d;
-                if (n > 0) {
-                    int lo[2], hi[2];
-                    const int nr = point_window(ex, ey, p.r_ext, lo, hi);
-                    float bq = 0.0f;
-                    int bid = kIntMax;
-                    auto key = [&](int i) { return (int)a.w.skey[g + i]; };
-                    visit(key, n, nr, lo, hi, [&](int i) {
-                        if (a.w.used[g + i]) return;
-                        const float dx = a.w.sx[g + i] - ex;
-                        const float dy = a.w.sy[g + i] - ey;
-                        const float q = dx * dx + dy * dy;
-                        if (!(q <= p.e_max)) return;
-                        const int id = a.w.sid[g + i];
-                        if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
-                    });
-                    if (want >= 0) atomicMin(claimT + want, t);
-                }
-            }
-            st.twant(t) = want;
-        }
-        active = __syncthreads_or(active);
-        if (!active) break;
-        for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
-            const int i = st.twant(t);
-            if (i >= 0 && claimT[i] == t) {
-                a.w.used[g + i] = 1;
-                st.tmask(t) |= 1u << j;
-                a.w.chits[(st.slot0 + t) * kPlanes + j] = a.w.sid[g + i];
-            }
-        }
-        __syncthreads();
-        if constexpr (S::kLarge) {
-            for (int t = t0 + threadIdx.x; t < t0 + nw; t += kT) {
-                const int i = st.twant(t);
-                if (i >= 0) claimT[i] = kIntMax;
-            }
-            __syncthreads();
-        }
+        if (!open) break;
     }
-    // the upstream state of the new tracks is unchanged by T3
     return true;
 }
 
-// T4: fit, plain decision, features.  Writes per-candidate outputs and the
-// event's output counts (plain mode).
-template <int kT, class S>
-__device__ void accept(S& st, const FindArgs& a, int e) {
-    Scalars& sc = *st.s;
-    const Params& p = a.p;
-    const int nt = sc.n_tracks;
-    if (threadIdx.x == 0) { sc.nout = 0; sc.nouthit = 0; sc.any = 0; }
-    __syncthreads();
-    int my_out = 0, my_hit = 0, my_all = 0;
-    for (int t = threadIdx.x; t < nt; t += kT) {
-        const int64_t slot = st.slot0 + t;
-        const uint32_t mask = st.tmask(t);
-        const int32_t* ch = a.w.chits + slot * kPlanes;
-        const FitResult f = fit_track_hits([&](int k, int) { return ch[k]; }, mask, a.clu_x, a.clu_y, p.z, p.sigma);
-        const int n = f.n;
-        const float lim = n == 3 ? p.c3 : p.c4;
-        const bool plain = f.chi2 / (float)f.ndof <= lim;
-        uint8_t fl = plain ? TRK_PLAIN : 0;
-        if (p.mode == 1) {
-            float raw[10];
-            raw_features(f, p.sigma, raw);
-            uint16_t fb[16];
-            std_features(raw, a.mlp_norm, fb);
-            uint4* out = reinterpret_cast<uint4*>(a.w.cfeat + slot * 16);
-            const uint4* src = reinterpret_cast<const uint4*>(fb);
-            out[0] = src[0];
-            out[1] = src[1];
-            fl |= TRK_LEARNED;
-        } else if (plain) {
-            fl |= TRK_ACCEPT;
-        }
-        a.w.cflags[slot] = fl;
-        if constexpr (!S::kLarge) a.w.cmask[slot] = mask;
-        my_all += n;
-        my_out += (fl & TRK_ACCEPT) ? 1 : 0;
-        my_hit += (fl & TRK_ACCEPT) ? n : 0;
-    }
-    atomicAdd(&sc.nout, my_out);
-    atomicAdd(&sc.nouthit, my_hit);
-    atomicAdd(&sc.any, my_all);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        a.w.ev_ncand[e] = nt;
-        a.w.ev_nout[e] = sc.nout;
-        a.w.ev_nouthit[e] = sc.nouthit;
-        a.w.ev_ncandhit[e] = sc.any;
-    }
-}
-
-// Whole event.  Returns false when the LDS tile was too small (event must be
-// redone by the large path); on return true the event's outputs are final.
+// Whole event.  Returns false when a capacity was too small (LDS tile: redo on
+// the large path; large path: overflow); on true the candidates are final.
 template <int kT, class S>
 __device__ bool find_event(S& st, const FindArgs& a, int e) {
     Scalars& sc = *st.s;
     if (threadIdx.x == 0) {
         sc.n_tracks = 0;
-        sc.wn[0] = sc.wn[1] = sc.wn[2] = 0;
-        sc.wg[0] = sc.wg[1] = sc.wg[2] = 0;
+        for (int i = 0; i < kRing; ++i) { sc.wn[i] = 0; sc.wg[i] = 0; }
     }
     for (int k = threadIdx.x; k <= kPlanes; k += kT) sc.cb[k] = a.clu_off[e * kPlanes + k];
     __syncthreads();
@@ -609,6 +605,7 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
         load_plane<kT>(st, a, k);
         if (sc.n_tracks > 0) forward<kT>(st, a, k);
         if (k <= kPlanes - 3) {
+            st.seed_k = k;
             if (!enumerate_seeds<kT>(st, a, k)) return false;
             if (sc.n_cand > 0) {
                 claim_seeds<kT>(st, a, k);
@@ -616,15 +613,16 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
             }
         }
     }
-    accept<kT>(st, a, e);
+    const int nt = sc.n_tracks;
+    if constexpr (!S::kLarge) {
+        for (int t = threadIdx.x; t < nt; t += kT) a.w.cmask[st.slot0 + t] = st.tmask(t);
+    }
+    if (threadIdx.x == 0) a.w.ev_ncand[e] = nt;
     return true;
 }
 
 __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) {
     a.w.ev_ncand[e] = 0;
-    a.w.ev_nout[e] = 0;
-    a.w.ev_nouthit[e] = 0;
-    a.w.ev_ncandhit[e] = 0;
     set_event_flag(a.status, e, flag, 1);
 }
 
@@ -632,7 +630,7 @@ template <int kT, int kP, int kTr, int kC>
 __global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
     __shared__ Tile<kP, kTr, kC> tile;
     __shared__ Scalars sc;
-    LdsStore<kP, kTr, kC> st{&tile, &sc, &a.w, 0};
+    LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
     while (true) {
         if (threadIdx.x == 0) {
             const int i = atomicAdd(a.w.counters + 1, 1);
@@ -697,6 +695,7 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
             a.w.g_slota[i] = ~0ull;
             a.w.g_slotb[i] = ~0u;
             a.w.cmask[i] = 0;
+            a.w.g_tkb[i] = 0;
         }
         st.slot0 = c0;
         st.cap_t = (int)((c1 - c0) / 3 + 1);
@@ -707,33 +706,98 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     }
 }
 
+// Acceptance of every candidate of an event (one workgroup per event): FP32
+// fit, chi2/ndof cut, features for the learned decision, output counts.
+__global__ __launch_bounds__(256) void k_accept(FindArgs a) {
+    __shared__ int s_out, s_hit, s_all;
+    const int e = blockIdx.x;
+    if (e >= a.n_events) return;
+    if (threadIdx.x == 0) { s_out = 0; s_hit = 0; s_all = 0; }
+    __syncthreads();
+    const Params& p = a.p;
+    const int nt = a.w.ev_ncand[e];
+    const int64_t slot0 = a.clu_off[e * kPlanes];
+    int my_out = 0, my_hit = 0, my_all = 0;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int64_t slot = slot0 + t;
+        const uint32_t mask = a.w.cmask[slot];
+        const int32_t* ch = a.w.chits + slot * kPlanes;
+        const FitResult f = fit_track_hits([&](int k, int) { return ch[k]; }, mask, a.clu_x, a.clu_y, p.z, p.sigma);
+        const float lim = f.n == 3 ? p.c3 : p.c4;
+        const bool plain = f.chi2 / (float)f.ndof <= lim;
+        uint8_t fl = plain ? TRK_PLAIN : 0;
+        if (p.mode == 1) {
+            float raw[10];
+            raw_features(f, p.sigma, raw);
+            uint16_t fb[16];
+            std_features(raw, a.mlp_norm, fb);
+            uint4* out = reinterpret_cast<uint4*>(a.w.cfeat + slot * 16);
+            const uint4* src = reinterpret_cast<const uint4*>(fb);
+            out[0] = src[0];
+            out[1] = src[1];
+            fl |= TRK_LEARNED;
+        } else if (plain) {
+            fl |= TRK_ACCEPT;
+        }
+        a.w.cflags[slot] = fl;
+        my_all += f.n;
+        my_out += (fl & TRK_ACCEPT) ? 1 : 0;
+        my_hit += (fl & TRK_ACCEPT) ? f.n : 0;
+    }
+    atomicAdd(&s_out, my_out);
+    atomicAdd(&s_hit, my_hit);
+    atomicAdd(&s_all, my_all);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.w.ev_nout[e] = s_out;
+        a.w.ev_nouthit[e] = s_hit;
+        a.w.ev_ncandhit[e] = s_all;
+    }
+}
+
 template <int kT, int kP, int kTr, int kC>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC>), dim3(grid), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
+template <int kT, int kP, int kTr, int kC>
+int occ_lds() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess) return 1;
+    return n;
+}
+
 }  // namespace
 
-
+// Tile shapes: (plane capacity, track capacity, seed candidates per step).
+#define VELO_TILES(X, T)               \
+    X(T, 0, 256, 256, 512)             \
+    X(T, 1, 512, 384, 768)             \
+    X(T, 2, 1024, 512, 1024)
 
 hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
-    hipError_t err = hipSuccess;
-#define VELO_TILE(T, P, TR, C) err = launch_lds<T, P, TR, C>(a, grid, s)
+#define VELO_CASE(T, L, P, TR, C) \
+    case T * 4 + L: return launch_lds<T, P, TR, C>(a, grid, s);
     switch (threads * 4 + tile) {
-        case 64 * 4 + 0: VELO_TILE(64, 256, 256, 512); break;
-        case 64 * 4 + 1: VELO_TILE(64, 512, 512, 1024); break;
-        case 64 * 4 + 2: VELO_TILE(64, 1024, 768, 1536); break;
-        case 128 * 4 + 0: VELO_TILE(128, 256, 256, 512); break;
-        case 128 * 4 + 1: VELO_TILE(128, 512, 512, 1024); break;
-        case 128 * 4 + 2: VELO_TILE(128, 1024, 768, 1536); break;
-        case 256 * 4 + 0: VELO_TILE(256, 256, 256, 512); break;
-        case 256 * 4 + 1: VELO_TILE(256, 512, 512, 1024); break;
-        case 256 * 4 + 2: VELO_TILE(256, 1024, 768, 1536); break;
+        VELO_TILES(VELO_CASE, 64)
+        VELO_TILES(VELO_CASE, 128)
+        VELO_TILES(VELO_CASE, 256)
         default: return hipErrorInvalidValue;
     }
-#undef VELO_TILE
-    return err;
+#undef VELO_CASE
+}
+
+int find_blocks_per_cu(int threads, int tile) {
+#define VELO_CASE(T, L, P, TR, C) \
+    case T * 4 + L: return occ_lds<T, P, TR, C>();
+    switch (threads * 4 + tile) {
+        VELO_TILES(VELO_CASE, 64)
+        VELO_TILES(VELO_CASE, 128)
+        VELO_TILES(VELO_CASE, 256)
+        default: return 1;
+    }
+#undef VELO_CASE
 }
 
 hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
@@ -741,41 +805,10 @@ hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-int find_tile_bytes(int threads, int tile) {
-    (void)threads;
-    switch (tile) {
-        case 0: return (int)(sizeof(Tile<256, 256, 512>) + sizeof(Scalars));
-        case 1: return (int)(sizeof(Tile<512, 512, 1024>) + sizeof(Scalars));
-        default: return (int)(sizeof(Tile<1024, 768, 1536>) + sizeof(Scalars));
-    }
-}
-
-}  // namespace velo
-
-namespace velo {
-
-namespace {
-template <int kT, int kP, int kTr, int kC>
-int occ_lds() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess) return 1;
-    return n;
-}
-}  // namespace
-
-int find_blocks_per_cu(int threads, int tile) {
-    switch (threads * 4 + tile) {
-        case 64 * 4 + 0: return occ_lds<64, 256, 256, 512>();
-        case 64 * 4 + 1: return occ_lds<64, 512, 512, 1024>();
-        case 64 * 4 + 2: return occ_lds<64, 1024, 768, 1536>();
-        case 128 * 4 + 0: return occ_lds<128, 256, 256, 512>();
-        case 128 * 4 + 1: return occ_lds<128, 512, 512, 1024>();
-        case 128 * 4 + 2: return occ_lds<128, 1024, 768, 1536>();
-        case 256 * 4 + 0: return occ_lds<256, 256, 256, 512>();
-        case 256 * 4 + 1: return occ_lds<256, 512, 512, 1024>();
-        case 256 * 4 + 2: return occ_lds<256, 1024, 768, 1536>();
-        default: return 1;
-    }
+hipError_t launch_accept(const FindArgs& a, hipStream_t s) {
+    if (a.n_events <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accept, dim3(a.n_events), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace velo

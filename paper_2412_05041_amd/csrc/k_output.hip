@@ -14,7 +14,6 @@ __global__ void k_reset(Work w, int n_events, int32_t* status) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (tid < 8) w.counters[tid] = 0;
-    for (int64_t i = tid; i < (int64_t)n_events * kPlanes; i += stride) w.lookback[i] = 0;
     if (status) {
         for (int64_t i = tid; i < kStatusHdr + n_events; i += stride) status[i] = 0;
     }

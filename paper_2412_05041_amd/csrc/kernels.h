@@ -80,6 +80,7 @@ hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s);
 hipError_t launch_find_large(const FindArgs& a, hipStream_t s);
+hipError_t launch_accept(const FindArgs& a, hipStream_t s);
 hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, hipStream_t s);

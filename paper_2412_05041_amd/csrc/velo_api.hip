@@ -129,7 +129,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
     w.ev_hbase = carve<int32_t>(cur, E);
     w.order = carve<int32_t>(cur, E);
     w.large = carve<int32_t>(cur, E);
-    w.lookback = carve<uint64_t>(cur, (int64_t)E * kPlanes);
+    w.seg_m = carve<int32_t>(cur, (int64_t)E * kPlanes);
     w.counters = carve<int32_t>(cur, 8);
     w.g_claim = carve<int32_t>(cur, C);
     w.g_slota = carve<uint64_t>(cur, C);
@@ -138,6 +138,10 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
     w.g_tty = carve<float>(cur, C);
     w.g_txb = carve<float>(cur, C);
     w.g_tyb = carve<float>(cur, C);
+    w.g_dtx = carve<float>(cur, C);
+    w.g_dty = carve<float>(cur, C);
+    w.g_dxb = carve<float>(cur, C);
+    w.g_dyb = carve<float>(cur, C);
     w.g_tkb = carve<int32_t>(cur, C);
     w.g_twant = carve<int32_t>(cur, C);
     w.n_large_blocks = 32;
@@ -192,6 +196,7 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     if (int rc = mark(c, 4, s, timed)) return rc;
     HIP_OK(launch_find_large(fa, s));
     if (int rc = mark(c, 5, s, timed)) return rc;
+    HIP_OK(launch_accept(fa, s));
     if (c->p.mode == 1) HIP_OK(launch_mlp_accept(c->mlp, fa, s));
     if (int rc = mark(c, 6, s, timed)) return rc;
     OutArgs oa{};

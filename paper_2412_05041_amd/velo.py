@@ -234,7 +234,7 @@ class Velo:
         _check(lib().velo_autotune(self.h, E, _ptr(clu_off), _ptr(clu_x), _ptr(clu_y), reps, ms, _stream()))
         return list(ms), self.get_launch()
 
-    STAGES = ("reset", "cluster", "order", "find_lds", "find_large", "learned", "scan", "output_fit")
+    STAGES = ("reset", "cluster", "order", "find_lds", "find_large", "accept", "scan", "output_fit")
 
     def set_timing(self, on: bool):
         _check(lib().velo_set_timing(self.h, 1 if on else 0))
