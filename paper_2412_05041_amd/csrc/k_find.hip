@@ -44,6 +44,23 @@ constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kRing = 5;  // planes k .. k+4 in the window
 
+#ifdef VELO_PHASE_TIMING
+__device__ unsigned long long g_phase[8];
+#define PHASE_T0() uint64_t ph_t = wall_clock64()
+#define PHASE(i)                                                        \
+    do {                                                                \
+        __syncthreads();                                                \
+        if (threadIdx.x == 0) {                                         \
+            const uint64_t now = wall_clock64();                        \
+            atomicAdd(&g_phase[i], (unsigned long long)(now - ph_t));   \
+            ph_t = now;                                                 \
+        }                                                               \
+    } while (0)
+#else
+#define PHASE_T0() (void)0
+#define PHASE(i) (void)0
+#endif
+
 // ---------------------------------------------------------------- storage
 // Accessors hide where a workgroup keeps its per-event state: the LDS tile
 // (normal events) or global scratch (large events).
@@ -601,15 +618,21 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
     }
     for (int k = threadIdx.x; k <= kPlanes; k += kT) sc.cb[k] = a.clu_off[e * kPlanes + k];
     __syncthreads();
+    PHASE_T0();
     for (int k = kPlanes - 1; k >= 0; --k) {
         load_plane<kT>(st, a, k);
+        PHASE(0);
         if (sc.n_tracks > 0) forward<kT>(st, a, k);
+        PHASE(1);
         if (k <= kPlanes - 3) {
             st.seed_k = k;
             if (!enumerate_seeds<kT>(st, a, k)) return false;
+            PHASE(2);
             if (sc.n_cand > 0) {
                 claim_seeds<kT>(st, a, k);
+                PHASE(3);
                 if (!create_tracks<kT>(st, a, k)) return false;
+                PHASE(4);
             }
         }
     }
@@ -804,6 +827,17 @@ hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_find_large<256>, dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
+
+#ifdef VELO_PHASE_TIMING
+extern "C" int velo_probe_phase(unsigned long long* out, int reset) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 8) != hipSuccess) return -1;
+    if (reset) {
+        unsigned long long z[8] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif
 
 hipError_t launch_accept(const FindArgs& a, hipStream_t s) {
     if (a.n_events <= 0) return hipSuccess;
