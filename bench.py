@@ -106,13 +106,16 @@ def main():
         v.mlp_set_weights(master, norm)
     v.reserve(E, batch.n_pix, batch.n_pix)
     off, ids = velo.to_device(batch)
+    tune_ms = None
     if args.launch:
         th, tl = (int(x) for x in args.launch.split(","))
         v.set_launch(th, tl)
     elif not args.no_autotune:
         c = v.cluster(off, ids, with_npix=False)
-        v.autotune(c["clu_off"], c["clu_x"], c["clu_y"], reps=2)
+        tune_ms, _ = v.autotune(c["clu_off"], c["clu_x"], c["clu_y"], reps=2)
         del c
+    else:
+        tune_ms = None
     bufs = v.pipeline_buffers(E, batch.n_pix)
     torch.cuda.synchronize()
 
@@ -183,6 +186,7 @@ def main():
             "tracks_per_event": T / E,
             "mode": args.mode,
             "launch": {"threads_per_event": th, "tile": tl},
+            "autotune_ms": tune_ms,
         },
         "efficiency": m["efficiency"],
         "ghost_rate": m["ghost_rate"],

@@ -29,9 +29,11 @@
 //     and the usual reach of the downstream completion (k+3, k+4);
 //   * T1/T3 conflicts: atomicMin of the track index on the wanted hit;
 //   * T2 greedy: rounds of "every candidate that holds the smallest key on all
-//     three of its hits wins" (two-phase 64/32-bit atomicMin on (q, h0) then
-//     (h1, h2)), which accepts exactly the candidates the sequential greedy
-//     accepts; winners are then ranked by key for their track indices.
+//     three of its hits wins"; the per-hit minimum of the 96-bit key is taken
+//     in two phases (64-bit atomicMin of (q, h0), then 32-bit atomicMin of
+//     (h1, h2) among the candidates holding that minimum on the hit).  This
+//     accepts exactly the candidates the sequential greedy accepts; winners are
+//     then ranked by key for their track indices.
 #include "fitfeat.h"
 #include "kernels.h"
 
@@ -43,6 +45,9 @@ constexpr float kPi = 3.14159265358979f;
 constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kRing = 5;  // planes k .. k+4 in the window
+constexpr int kLutSmall = 256;   // key buckets of an LDS-tile plane
+constexpr int kLutLarge = 4096;  // key buckets of a large-event plane
+constexpr float kKeysPerRad = 10430.378350470453f;  // 2^16 / (2 pi)
 
 #ifdef VELO_PHASE_TIMING
 __device__ unsigned long long g_phase[8];
@@ -65,26 +70,27 @@ __device__ unsigned long long g_phase[8];
 // Accessors hide where a workgroup keeps its per-event state: the LDS tile
 // (normal events) or global scratch (large events).
 
-template <int kP, int kT, int kC>
+template <int kP, int kT, int kC, int kN>
 struct Tile {
     float wx[kRing][kP];
     float wy[kRing][kP];
-    uint64_t slota[3][kP];  // seeding planes k, k+1, k+2
-    uint32_t slotb[3][kP];
+    uint64_t slota[3][kP];  // seeding planes k, k+1, k+2 (then winner keys)
+    uint32_t slotb[3][kP];  // (then winner list, then downstream claims)
     int32_t claim[kP];
-    int32_t claimT[kP];
     uint16_t wid[kRing][kP];  // plane-local cluster index
     uint16_t wk[kRing][kP];
     uint8_t wu[kRing][kP];
-    // tracks: upstream end (T1) and downstream end (T3)
+    // tracks: upstream end (T1); downstream end (T3) of the current step's new tracks
     float ttx[kT], tty[kT], txb[kT], tyb[kT];
-    float dtx[kT], dty[kT], dxb[kT], dyb[kT];
     uint32_t tmask[kT];
-    int32_t twant[kT];
-    int8_t tkb[kT], dkb[kT];
+    int16_t twant[kT];
+    int8_t tkb[kT];
+    float dtx[kN], dty[kN], dxb[kN], dyb[kN];
+    int8_t dkb[kN];
     float cq[kC];
     uint16_t cp[kC][3];
     uint8_t calive[kC];
+    uint16_t lut[kRing][kLutSmall + 1];  // first position of each key bucket
 };
 
 struct Scalars {
@@ -94,13 +100,14 @@ struct Scalars {
     int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
 };
 
-template <int kP, int kT, int kC>
+template <int kP, int kT, int kC, int kN>
 struct LdsStore {
     static constexpr bool kLarge = false;
-    Tile<kP, kT, kC>* t;
+    Tile<kP, kT, kC, kN>* t;
     Scalars* s;
     int64_t slot0;
     int seed_k = 0;
+    int dbase = 0;  // first track of the downstream-state window
     __device__ float X(int sl, int i) const { return t->wx[sl][i]; }
     __device__ float Y(int sl, int i) const { return t->wy[sl][i]; }
     __device__ int K(int sl, int i) const { return t->wk[sl][i]; }
@@ -108,23 +115,23 @@ struct LdsStore {
     __device__ int64_t ID(int sl, int i) const { return s->wg[sl] + t->wid[sl][i]; }
     __device__ uint8_t& U(int sl, int i) { return t->wu[sl][i]; }
     __device__ int32_t* claim(int) { return t->claim; }
-    __device__ int32_t* claimT(int64_t) { return t->claimT; }
+    __device__ int32_t* claimT(int64_t) { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
     __device__ uint64_t* slotA(int role) { return t->slota[role]; }
     __device__ uint32_t* slotB(int role) { return t->slotb[role]; }
     __device__ float& ttx(int i) { return t->ttx[i]; }
     __device__ float& tty(int i) { return t->tty[i]; }
     __device__ float& txb(int i) { return t->txb[i]; }
     __device__ float& tyb(int i) { return t->tyb[i]; }
-    __device__ float& dtx(int i) { return t->dtx[i]; }
-    __device__ float& dty(int i) { return t->dty[i]; }
-    __device__ float& dxb(int i) { return t->dxb[i]; }
-    __device__ float& dyb(int i) { return t->dyb[i]; }
+    __device__ float& dtx(int i) { return t->dtx[i - dbase]; }
+    __device__ float& dty(int i) { return t->dty[i - dbase]; }
+    __device__ float& dxb(int i) { return t->dxb[i - dbase]; }
+    __device__ float& dyb(int i) { return t->dyb[i - dbase]; }
     __device__ int tkb(int i) const { return t->tkb[i]; }
     __device__ void set_tkb(int i, int v) { t->tkb[i] = (int8_t)v; }
-    __device__ int dkb(int i) const { return t->dkb[i]; }
-    __device__ void set_dkb(int i, int v) { t->dkb[i] = (int8_t)v; }
+    __device__ int dkb(int i) const { return t->dkb[i - dbase]; }
+    __device__ void set_dkb(int i, int v) { t->dkb[i - dbase] = (int8_t)v; }
     __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
-    __device__ int32_t& twant(int i) { return t->twant[i]; }
+    __device__ int16_t& twant(int i) { return t->twant[i]; }
     __device__ float& cq(int i) { return t->cq[i]; }
     __device__ int cp(int i, int j) const { return t->cp[i][j]; }
     __device__ void set_cp(int i, int a, int b, int c) {
@@ -135,6 +142,10 @@ struct LdsStore {
     __device__ uint32_t* wtmp() { return &t->slotb[0][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
+    __device__ int cap_new() const { return kN; }
+    static constexpr int kLutN = kLutSmall;
+    static constexpr int kLutShift = 8;
+    __device__ uint16_t* lut(int sl) { return t->lut[sl]; }
 };
 
 struct GlobalStore {
@@ -180,6 +191,12 @@ struct GlobalStore {
     __device__ uint32_t* wtmp() { return w->g_slotb + s->cb[seed_k]; }
     __device__ int cap_tracks() const { return cap_t; }
     __device__ int cap_cand() const { return (int)w->pool_cap; }
+    __device__ int cap_new() const { return cap_t; }
+    int dbase = 0;
+    static constexpr int kLutN = kLutLarge;
+    static constexpr int kLutShift = 4;
+    uint16_t (*luts)[kLutLarge + 1] = nullptr;  // LDS
+    __device__ uint16_t* lut(int sl) { return luts[sl]; }
 };
 
 // ---------------------------------------------------------------- windows
@@ -220,23 +237,59 @@ __device__ __forceinline__ int lower_key(KF key, int n, int v) {
     return lo;
 }
 
-// Visits every position of a key-sorted plane whose key lies in the ranges.
-template <class KF, class F>
-__device__ __forceinline__ void visit(KF key, int n, int nr, const int* lo, const int* hi, F f) {
+// Lower bound through a bucket index: lut[b] = first position whose key
+// has bucket >= b, then a short forward scan.
+template <int kShift, class KF>
+__device__ __forceinline__ int lower_lut(const uint16_t* lut, KF key, int n, int v) {
+    int i = lut[v >> kShift];
+    while (i < n && key(i) < v) ++i;
+    return i;
+}
+
+// Visits every position of a key-sorted plane whose key lies in the ranges;
+// lower(v) is the first position with key >= v.
+template <class LF, class KF, class F>
+__device__ __forceinline__ void visit(LF lower, KF key, int n, int nr, const int* lo, const int* hi, F f) {
     for (int r = 0; r < nr; ++r) {
-        for (int i = lower_key(key, n, lo[r]); i < n && key(i) <= hi[r]; ++i) f(i);
+        for (int i = lower(lo[r]); i < n && key(i) <= hi[r]; ++i) f(i);
     }
 }
 
+// Key ranges covering keys [a - m, b + m] on the key circle (a <= b, as plain
+// integers possibly outside [0, 65535]).
+__device__ __forceinline__ int key_span(int a, int b, int m, int* lo, int* hi) {
+    int l = a - m, h = b + m;
+    if (h - l >= 65535) { lo[0] = 0; hi[0] = 65535; return 1; }
+    if (l < 0) {
+        lo[0] = l + 65536; hi[0] = 65535;
+        lo[1] = 0; hi[1] = h;
+        return 2;
+    }
+    if (h > 65535) {
+        lo[0] = l; hi[0] = 65535;
+        lo[1] = 0; hi[1] = h - 65536;
+        return 2;
+    }
+    lo[0] = l; hi[0] = h;
+    return 1;
+}
+
+// Half-width in keys of the azimuth range subtended by a disc of radius R seen
+// at distance r (asin(R/r) plus margins), or -1 when the whole circle is needed.
+__device__ __forceinline__ int disc_keys(float R, float r) {
+    if (!(r > R * 1.001f + 1e-3f)) return -1;
+    return (int)ceilf((asinf(R / r) * 1.0001f + 2e-4f) * kKeysPerRad) + 2;
+}
+
 // Best unused hit (q, index) within e_max of (ex, ey) on a staged plane.
-template <class KF, class UF, class XF, class YF, class IF>
-__device__ __forceinline__ int best_hit(KF key, UF used, XF xf, YF yf, IF idf, int n, float ex, float ey,
+template <class LF, class KF, class UF, class XF, class YF, class IF>
+__device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf, IF idf, int n, float ex, float ey,
                                         const Params& p) {
     int lo[2], hi[2];
     const int nr = point_window(ex, ey, p.r_ext, lo, hi);
     float bq = 0.0f;
     int bid = kIntMax, want = -1;
-    visit(key, n, nr, lo, hi, [&](int i) {
+    visit(lower, key, n, nr, lo, hi, [&](int i) {
         if (used(i)) return;
         const float dx = xf(i) - ex;
         const float dy = yf(i) - ey;
@@ -267,8 +320,8 @@ __device__ void load_plane(S& st, const FindArgs& a, int k) {
         sc.wn[sl] = (int)(sc.cb[k + 1] - sc.cb[k]);
     }
     __syncthreads();
+    const int n = sc.wn[sl];
     if constexpr (!S::kLarge) {
-        const int n = sc.wn[sl];
         const int64_t g = sc.wg[sl];
         auto* t = st.t;
         for (int i = threadIdx.x; i < n; i += kT) {
@@ -281,6 +334,21 @@ __device__ void load_plane(S& st, const FindArgs& a, int k) {
         }
         __syncthreads();
     }
+    // bucket index: lut[b] = first position whose key bucket is >= b
+    uint16_t* lut = st.lut(sl);
+    constexpr int kShift = S::kLutShift, kN = S::kLutN;
+    if (n == 0) {
+        for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
+    } else {
+        for (int i = threadIdx.x; i < n; i += kT) {
+            const int bi = st.K(sl, i) >> kShift;
+            const int bp = i ? (st.K(sl, i - 1) >> kShift) : -1;
+            for (int b = bp + 1; b <= bi; ++b) lut[b] = (uint16_t)i;
+            if (i == n - 1)
+                for (int b = bi + 1; b <= kN; ++b) lut[b] = (uint16_t)n;
+        }
+    }
+    __syncthreads();
 }
 
 // T1: extend open tracks onto plane k.
@@ -299,7 +367,10 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             const float d = p.z[k] - p.z[kb];
             const float ex = st.txb(t) + st.ttx(t) * d;
             const float ey = st.tyb(t) + st.tty(t) * d;
-            want = best_hit([&](int i) { return st.K(sl, i); }, [&](int i) { return st.U(sl, i); },
+            const uint16_t* lut = st.lut(sl);
+            auto key = [&](int i) { return st.K(sl, i); };
+            want = best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, n, v); }, key,
+                            [&](int i) { return st.U(sl, i); },
                             [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
                             [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
             if (want >= 0) atomicMin(claim + want, t);
@@ -346,18 +417,25 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     const int cap = st.cap_cand();
     auto key1 = [&](int i) { return st.K(s1, i); };
     auto key2 = [&](int i) { return st.K(s2, i); };
+    const uint16_t* lut1 = st.lut(s1);
+    const uint16_t* lut2 = st.lut(s2);
+    auto lower1 = [&](int v) { return lower_lut<S::kLutShift>(lut1, key1, n1, v); };
+    auto lower2 = [&](int v) { return lower_lut<S::kLutShift>(lut2, key2, n2, v); };
     for (int i0 = threadIdx.x; i0 < n0; i0 += kT) {
         if (st.U(s0, i0)) continue;
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
-        // h2 lies within asin(D / r0) of h0's azimuth (outward line passing within D of the axis)
+        const int k0 = st.K(s0, i0);
+        // An outward line through h0 passing within D of the axis keeps every
+        // later point within asin(D/r0) of h0's azimuth, and its radius grows:
+        // h2 lies in that wedge, and the predicted middle point lies between
+        // the azimuths of h0 and h2 at radius >= r0, so h1 is within
+        // asin(R_mid/r0) of that arc.
         const float r0 = sqrtf(x0 * x0 + y0 * y0);
-        int lo[2], hi[2], nr;
-        if (!(r0 > p.r_seed * 1.001f + 1e-3f)) {
-            lo[0] = 0; hi[0] = 65535; nr = 1;
-        } else {
-            nr = key_ranges(atan2f(y0, x0), asinf(p.r_seed / r0) * 1.0001f + 2e-4f, lo, hi);
-        }
-        visit(key2, n2, nr, lo, hi, [&](int i2) {
+        const int mD = disc_keys(p.r_seed, r0);
+        const int m1 = disc_keys(p.r_mid, r0);
+        int lo[2], hi[2];
+        const int nr = mD < 0 ? (lo[0] = 0, hi[0] = 65535, 1) : key_span(k0, k0, mD, lo, hi);
+        visit(lower2, key2, n2, nr, lo, hi, [&](int i2) {
             if (st.U(s2, i2)) return;
             const float tx = (st.X(s2, i2) - x0) / dz2;
             const float ty = (st.Y(s2, i2) - y0) / dz2;
@@ -367,9 +445,12 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
             if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) return;
             const float ex = x0 + tx * dz1;
             const float ey = y0 + ty * dz1;
+            int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
+            kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
             int lo1[2], hi1[2];
-            const int nr1 = point_window(ex, ey, p.r_mid, lo1, hi1);
-            visit(key1, n1, nr1, lo1, hi1, [&](int i1) {
+            const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
+                                   : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
+            visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) {
                 if (st.U(s1, i1)) return;
                 const float dx = st.X(s1, i1) - ex;
                 const float dy = st.Y(s1, i1) - ey;
@@ -423,16 +504,16 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
             atomicMin((unsigned long long*)(A2 + st.cp(c, 2)), kA);
         }
         __syncthreads();
+        // per hit: among the candidates holding the smallest (q, h0) there,
+        // the smallest (h1, h2) -- the per-hit minimum of the full key
         for (int c = threadIdx.x; c < nc; c += kT) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             const uint64_t kA = keyA(c);
-            if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA) {
-                const uint32_t kB = keyB(c);
-                atomicMin(B0 + i0, kB);
-                atomicMin(B1 + i1, kB);
-                atomicMin(B2 + i2, kB);
-            }
+            const uint32_t kB = keyB(c);
+            if (A0[i0] == kA) atomicMin(B0 + i0, kB);
+            if (A1[i1] == kA) atomicMin(B1 + i1, kB);
+            if (A2[i2] == kA) atomicMin(B2 + i2, kB);
         }
         __syncthreads();
         for (int c = threadIdx.x; c < nc; c += kT) {
@@ -470,9 +551,9 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
 // One downstream completion step (plane j) of the tracks [t0, t1).  The plane
 // is read through the accessors given (LDS ring or global staging).  Returns
 // (uniformly) whether any track was still open.
-template <int kT, class S, class KF, class UF, class XF, class YF, class IF>
-__device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, KF key,
-                               UF used, XF xf, YF yf, IF idf, int64_t gbase) {
+template <int kT, class S, class LF, class KF, class UF, class XF, class YF, class IF>
+__device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, LF lower,
+                               KF key, UF used, XF xf, YF yf, IF idf, int64_t gbase) {
     const Params& p = a.p;
     if constexpr (!S::kLarge) {
         for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
@@ -488,7 +569,7 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
             const float ex = st.dxb(t) + st.dtx(t) * d;
             const float ey = st.dyb(t) + st.dty(t) * d;
             if (n > 0) {
-                want = best_hit(key, used, xf, yf, idf, n, ex, ey, p);
+                want = best_hit(lower, key, used, xf, yf, idf, n, ex, ey, p);
                 if (want >= 0) atomicMin(claimT + want, t);
             }
         }
@@ -542,8 +623,9 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     }
     __syncthreads();
     const int nw = sc.n_acc;
-    if (t0 + nw > st.cap_tracks()) return false;
+    if (t0 + nw > st.cap_tracks() || nw > st.cap_new()) return false;
     if (nw == 0) return true;
+    st.dbase = t0;
     for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
         wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
@@ -588,16 +670,21 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
         bool open;
         if (!S::kLarge && j < k + kRing) {
             const int sl = j % kRing;
-            open = complete_plane<kT>(st, a, j, t0, t0 + nw, sc.wn[sl], st.claimT(0),
-                                      [&](int i) { return st.K(sl, i); },
+            const int nj = sc.wn[sl];
+            const uint16_t* lut = st.lut(sl);
+            auto key = [&](int i) { return st.K(sl, i); };
+            open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0),
+                                      [&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
                                       [&](int i) -> uint8_t& { return st.U(sl, i); },
                                       [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
                                       [&](int i) { return st.L(sl, i); }, sc.wg[sl]);
         } else {
             const int64_t g = sc.cb[j];
             const Work& w = a.w;
-            open = complete_plane<kT>(st, a, j, t0, t0 + nw, (int)(sc.cb[j + 1] - g), st.claimT(g),
-                                      [&](int i) { return (int)w.skey[g + i]; },
+            const int nj = (int)(sc.cb[j + 1] - g);
+            auto key = [&](int i) { return (int)w.skey[g + i]; };
+            open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
+                                      [&](int v) { return lower_key(key, nj, v); }, key,
                                       [&](int i) -> uint8_t& { return w.used[g + i]; },
                                       [&](int i) { return w.sx[g + i]; }, [&](int i) { return w.sy[g + i]; },
                                       [&](int i) { return (int)(w.sid[g + i] - g); }, g);
@@ -649,11 +736,11 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
     set_event_flag(a.status, e, flag, 1);
 }
 
-template <int kT, int kP, int kTr, int kC>
+template <int kT, int kP, int kTr, int kC, int kN>
 __global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
-    __shared__ Tile<kP, kTr, kC> tile;
+    __shared__ Tile<kP, kTr, kC, kN> tile;
     __shared__ Scalars sc;
-    LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
+    LdsStore<kP, kTr, kC, kN> st{&tile, &sc, 0};
     while (true) {
         if (threadIdx.x == 0) {
             const int i = atomicAdd(a.w.counters + 1, 1);
@@ -688,7 +775,9 @@ __global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
 template <int kT>
 __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     __shared__ Scalars sc;
+    __shared__ uint16_t luts[kRing][kLutLarge + 1];
     GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
+    st.luts = luts;
     const int n_large = a.w.counters[2];
     while (true) {
         if (threadIdx.x == 0) {
@@ -778,30 +867,31 @@ __global__ __launch_bounds__(256) void k_accept(FindArgs a) {
     }
 }
 
-template <int kT, int kP, int kTr, int kC>
+template <int kT, int kP, int kTr, int kC, int kN>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC>), dim3(grid), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, kN>), dim3(grid), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int kT, int kP, int kTr, int kC>
+template <int kT, int kP, int kTr, int kC, int kN>
 int occ_lds() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, kN>, kT, 0) != hipSuccess)
+        return 1;
     return n;
 }
 
 }  // namespace
 
-// Tile shapes: (plane capacity, track capacity, seed candidates per step).
+// Tile shapes: (plane capacity, tracks, seed candidates per step, new tracks per step).
 #define VELO_TILES(X, T)               \
-    X(T, 0, 256, 256, 512)             \
-    X(T, 1, 512, 384, 768)             \
-    X(T, 2, 1024, 512, 1024)
+    X(T, 0, 256, 320, 384, 64)         \
+    X(T, 1, 512, 640, 512, 128)        \
+    X(T, 2, 1024, 1024, 1024, 256)
 
 hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
-#define VELO_CASE(T, L, P, TR, C) \
-    case T * 4 + L: return launch_lds<T, P, TR, C>(a, grid, s);
+#define VELO_CASE(T, L, P, TR, C, N) \
+    case T * 4 + L: return launch_lds<T, P, TR, C, N>(a, grid, s);
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
@@ -812,8 +902,8 @@ hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, h
 }
 
 int find_blocks_per_cu(int threads, int tile) {
-#define VELO_CASE(T, L, P, TR, C) \
-    case T * 4 + L: return occ_lds<T, P, TR, C>();
+#define VELO_CASE(T, L, P, TR, C, N) \
+    case T * 4 + L: return occ_lds<T, P, TR, C, N>();
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)

@@ -228,11 +228,32 @@ class Velo:
                                    b["hit_cap"], _ptr(b["status"]), _stream()))
         return bufs
 
-    def autotune(self, clu_off, clu_x, clu_y, reps=3):
+    def autotune(self, clu_off, clu_x, clu_y, reps=3, cache=None, key=None):
+        """Times the 9 finder launch configurations on these clusters and keeps
+        the fastest.  With cache (a JSON file) and key (a workload label), a
+        stored choice for (device arch, CU count, key) is reused instead."""
+        ident = None
+        if cache is not None and key is not None:
+            import json
+            p = torch.cuda.get_device_properties(self.device)
+            ident = f"{getattr(p, 'gcnArchName', p.name)}|{p.multi_processor_count}|{key}"
+            table = json.load(open(cache)) if os.path.exists(cache) else {}
+            if ident in table:
+                th, tl = table[ident]["launch"]
+                self.set_launch(th, tl)
+                return table[ident]["ms"], (th, tl)
         E = (clu_off.numel() - 1) // N_PLANES
         ms = (C.c_float * 9)()
         _check(lib().velo_autotune(self.h, E, _ptr(clu_off), _ptr(clu_x), _ptr(clu_y), reps, ms, _stream()))
-        return list(ms), self.get_launch()
+        res = (list(ms), self.get_launch())
+        if ident is not None:
+            import json
+            table = json.load(open(cache)) if os.path.exists(cache) else {}
+            table[ident] = {"launch": list(res[1]), "ms": res[0]}
+            tmp = cache + ".tmp"
+            json.dump(table, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache)
+        return res
 
     STAGES = ("reset", "cluster", "order", "find_lds", "find_large", "accept", "scan", "output_fit")
 

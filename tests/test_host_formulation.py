@@ -1,0 +1,136 @@
+"""CPU checks of the GPU's parallel formulation (host re-statements, no device).
+
+1. Greedy claiming by rounds of local minima -- the rule the finder kernel runs
+   with two-phase atomicMin -- accepts exactly the candidates of the sequential
+   greedy over (q, h0, h1, h2).
+2. The azimuth-key windows used to prune searches contain every hit that passes
+   the exact FP32 cut (brute force over random geometry, float32 arithmetic).
+"""
+import math
+
+import numpy as np
+import pytest
+
+f32 = np.float32
+
+
+def sequential_greedy(cands):
+    used, acc = set(), []
+    for c in sorted(cands):
+        q, h0, h1, h2 = c
+        hs = (("a", h0), ("b", h1), ("c", h2))
+        if any(h in used for h in hs):
+            continue
+        used.update(hs)
+        acc.append(c)
+    return acc
+
+
+def rounds_of_local_minima(cands):
+    alive = {i: c for i, c in enumerate(cands)}
+    used, acc, rounds = set(), [], 0
+    while alive:
+        rounds += 1
+        slot_a, slot_b = {}, {}
+        for c in alive.values():  # phase A: (q, h0) min on every hit
+            for h in (("a", c[1]), ("b", c[2]), ("c", c[3])):
+                slot_a[h] = min(slot_a.get(h, (math.inf, 0)), (c[0], c[1]))
+        for c in alive.values():  # phase B: (h1, h2) among the holders of each hit's phase-A minimum
+            for h in (("a", c[1]), ("b", c[2]), ("c", c[3])):
+                if slot_a[h] == (c[0], c[1]):
+                    slot_b[h] = min(slot_b.get(h, (math.inf, 0)), (c[2], c[3]))
+        winners = []
+        for i, c in alive.items():
+            hs = (("a", c[1]), ("b", c[2]), ("c", c[3]))
+            if all(slot_a[h] == (c[0], c[1]) for h in hs) and all(slot_b.get(h) == (c[2], c[3]) for h in hs):
+                winners.append(i)
+        assert winners, "a round must make progress"
+        for i in winners:
+            c = alive.pop(i)
+            used.update((("a", c[1]), ("b", c[2]), ("c", c[3])))
+            acc.append(c)
+        for i in [i for i, c in alive.items() if (("a", c[1]) in used or ("b", c[2]) in used or ("c", c[3]) in used)]:
+            alive.pop(i)
+    return sorted(acc), rounds
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_rounds_equal_sequential_greedy(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    pool = int(rng.integers(2, 40))
+    qs = rng.integers(0, 6, n).astype(float) if seed % 3 == 0 else rng.random(n)  # many exact ties
+    cands = sorted({(float(qs[i]), int(rng.integers(pool)), int(rng.integers(pool)), int(rng.integers(pool)))
+                    for i in range(n)})
+    acc, _ = rounds_of_local_minima(cands)
+    assert acc == sorted(sequential_greedy(cands))
+
+
+# ---------------------------------------------------------------- key windows
+
+KEYS_PER_RAD = f32(10430.378350470453)
+PI = f32(3.14159265358979)
+
+
+def phi_key(x, y):
+    u = (np.arctan2(y, x).astype(f32) + PI) * KEYS_PER_RAD
+    return np.clip(u.astype(np.int64), 0, 65535)
+
+
+def disc_keys(R, r):
+    """Half-width in keys of asin(R/r) plus margins (None = whole circle)."""
+    if not (r > R * 1.001 + 1e-3):
+        return None
+    return int(math.ceil((math.asin(R / r) * 1.0001 + 2e-4) * float(KEYS_PER_RAD))) + 2
+
+
+def in_span(k, a, b, m):
+    if m is None:
+        return True
+    lo, hi = a - m, b + m
+    return any(lo <= kk <= hi for kk in (k, k - 65536, k + 65536))
+
+
+def test_seed_windows_contain_every_passing_triplet():
+    rng = np.random.default_rng(7)
+    D2, S, TMAX = f32(9.0), f32(0.09), f32(0.4)
+    R_seed, R_mid = math.sqrt(9.0) * 1.0001 + 1e-6, math.sqrt(0.09) * 1.0001 + 1e-6
+    dz1, dz2 = f32(41.5), f32(84.2)
+    n = 400000
+    # h0 anywhere outside 5 mm; h2 = h0 + t dz2 + jitter (mostly near-pointing lines)
+    r0 = rng.uniform(5.0, 40.0, n)
+    ph0 = rng.uniform(-math.pi, math.pi, n)
+    x0 = (r0 * np.cos(ph0)).astype(f32)
+    y0 = (r0 * np.sin(ph0)).astype(f32)
+    ang = ph0 + rng.normal(0, 0.25, n)
+    tt = rng.uniform(0.0, 0.45, n)
+    x2 = (x0 + tt * np.cos(ang) * float(dz2) + rng.normal(0, 0.3, n)).astype(f32)
+    y2 = (y0 + tt * np.sin(ang) * float(dz2) + rng.normal(0, 0.3, n)).astype(f32)
+    tx = (x2 - x0) / dz2
+    ty = (y2 - y0) / dz2
+    ok = (np.abs(tx) <= TMAX) & (np.abs(ty) <= TMAX) & (x0 * tx + y0 * ty > 0)
+    cr = x0 * ty - y0 * tx
+    ok &= cr * cr <= D2 * (tx * tx + ty * ty)
+    idx = np.nonzero(ok)[0]
+    assert idx.size > 10000
+    k0 = phi_key(x0[idx], y0[idx])
+    k2 = phi_key(x2[idx], y2[idx])
+    ex = x0[idx] + tx[idx] * dz1
+    ey = y0[idx] + ty[idx] * dz1
+    # middle hits on the boundary of the S3 disc (and inside)
+    a1 = rng.uniform(0, 2 * math.pi, idx.size)
+    rr = np.sqrt(rng.uniform(0, 1, idx.size)) * 0.3
+    x1 = (ex + rr * np.cos(a1)).astype(f32)
+    y1 = (ey + rr * np.sin(a1)).astype(f32)
+    dx, dy = x1 - ex, y1 - ey
+    s3 = dx * dx + dy * dy <= S
+    k1 = phi_key(x1, y1)
+    for j in range(idx.size):
+        rj = math.sqrt(float(x0[idx[j]]) ** 2 + float(y0[idx[j]]) ** 2)
+        mD = disc_keys(R_seed, rj)
+        assert in_span(int(k2[j]), int(k0[j]), int(k0[j]), mD), j
+        if s3[j]:
+            kd = int(k2[j]) - int(k0[j])
+            kd = kd - 65536 if kd > 32767 else (kd + 65536 if kd < -32768 else kd)
+            m1 = disc_keys(R_mid, rj)
+            assert in_span(int(k1[j]), int(k0[j]) + min(kd, 0), int(k0[j]) + max(kd, 0), m1), j
