@@ -72,6 +72,7 @@ struct Work {
     float* g_dxb;
     float* g_dyb;
     int32_t* g_tkb;       // planes of the two ends (bits 0-7 upstream, 8-15 downstream)
+    int32_t* g_enum;      // seed-enumeration scratch, 6 per cluster
     int32_t* g_twant;
     // large-event seed pool: per block of the large kernel
     float* p_q;

@@ -70,7 +70,7 @@ __device__ unsigned long long g_phase[8];
 // Accessors hide where a workgroup keeps its per-event state: the LDS tile
 // (normal events) or global scratch (large events).
 
-template <int kP, int kT, int kC, int kN>
+template <int kP, int kT, int kC>
 struct Tile {
     float wx[kRing][kP];
     float wy[kRing][kP];
@@ -80,13 +80,12 @@ struct Tile {
     uint16_t wid[kRing][kP];  // plane-local cluster index
     uint16_t wk[kRing][kP];
     uint8_t wu[kRing][kP];
-    // tracks: upstream end (T1); downstream end (T3) of the current step's new tracks
+    // tracks: upstream end (T1); the downstream end (T3) of a step's new tracks
+    // lives in the seeding-slot memory once the seeds are claimed
     float ttx[kT], tty[kT], txb[kT], tyb[kT];
     uint32_t tmask[kT];
     int16_t twant[kT];
     int8_t tkb[kT];
-    float dtx[kN], dty[kN], dxb[kN], dyb[kN];
-    int8_t dkb[kN];
     float cq[kC];
     uint16_t cp[kC][3];
     uint8_t calive[kC];
@@ -94,20 +93,22 @@ struct Tile {
 };
 
 struct Scalars {
-    int n_tracks, n_cand, n_acc, event;
+    int n_tracks, n_cand, n_acc, event, n_pairs;
+    int wsum[16];            // per-wave partial sums of block scans
     int wn[kRing];
     int64_t wg[kRing];       // staged (= cluster) base of the plane in each ring slot
     int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
 };
 
-template <int kP, int kT, int kC, int kN>
+template <int kP, int kT, int kC>
 struct LdsStore {
     static constexpr bool kLarge = false;
-    Tile<kP, kT, kC, kN>* t;
+    Tile<kP, kT, kC>* t;
     Scalars* s;
     int64_t slot0;
     int seed_k = 0;
     int dbase = 0;  // first track of the downstream-state window
+    int dn = 0;     // its length
     __device__ float X(int sl, int i) const { return t->wx[sl][i]; }
     __device__ float Y(int sl, int i) const { return t->wy[sl][i]; }
     __device__ int K(int sl, int i) const { return t->wk[sl][i]; }
@@ -122,14 +123,18 @@ struct LdsStore {
     __device__ float& tty(int i) { return t->tty[i]; }
     __device__ float& txb(int i) { return t->txb[i]; }
     __device__ float& tyb(int i) { return t->tyb[i]; }
-    __device__ float& dtx(int i) { return t->dtx[i - dbase]; }
-    __device__ float& dty(int i) { return t->dty[i - dbase]; }
-    __device__ float& dxb(int i) { return t->dxb[i - dbase]; }
-    __device__ float& dyb(int i) { return t->dyb[i - dbase]; }
+    __device__ float* dst() const { return reinterpret_cast<float*>(&t->slota[0][0]); }
+    __device__ float& dtx(int i) { return dst()[i - dbase]; }
+    __device__ float& dty(int i) { return dst()[dn + i - dbase]; }
+    __device__ float& dxb(int i) { return dst()[2 * dn + i - dbase]; }
+    __device__ float& dyb(int i) { return dst()[3 * dn + i - dbase]; }
     __device__ int tkb(int i) const { return t->tkb[i]; }
     __device__ void set_tkb(int i, int v) { t->tkb[i] = (int8_t)v; }
-    __device__ int dkb(int i) const { return t->dkb[i - dbase]; }
-    __device__ void set_dkb(int i, int v) { t->dkb[i - dbase] = (int8_t)v; }
+    __device__ int dkb(int i) const { return reinterpret_cast<const int8_t*>(dst() + 4 * dn)[i - dbase]; }
+    __device__ void set_dkb(int i, int v) { reinterpret_cast<int8_t*>(dst() + 4 * dn)[i - dbase] = (int8_t)v; }
+    // enumeration scratch (seeding slots are free before the claiming rounds)
+    __device__ int32_t* pref() { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
+    __device__ int32_t* ebuf() { return reinterpret_cast<int32_t*>(&t->slota[0][0]); }
     __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
     __device__ int16_t& twant(int i) { return t->twant[i]; }
     __device__ float& cq(int i) { return t->cq[i]; }
@@ -142,7 +147,6 @@ struct LdsStore {
     __device__ uint32_t* wtmp() { return &t->slotb[0][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
-    __device__ int cap_new() const { return kN; }
     static constexpr int kLutN = kLutSmall;
     static constexpr int kLutShift = 8;
     __device__ uint16_t* lut(int sl) { return t->lut[sl]; }
@@ -191,8 +195,9 @@ struct GlobalStore {
     __device__ uint32_t* wtmp() { return w->g_slotb + s->cb[seed_k]; }
     __device__ int cap_tracks() const { return cap_t; }
     __device__ int cap_cand() const { return (int)w->pool_cap; }
-    __device__ int cap_new() const { return cap_t; }
-    int dbase = 0;
+    int dbase = 0, dn = 0;
+    __device__ int32_t* pref() { return w->g_enum + 6 * s->cb[seed_k]; }
+    __device__ int32_t* ebuf() { return w->g_enum + 6 * s->cb[seed_k] + s->cb[seed_k + 1] - s->cb[seed_k] + 1; }
     static constexpr int kLutN = kLutLarge;
     static constexpr int kLutShift = 4;
     uint16_t (*luts)[kLutLarge + 1] = nullptr;  // LDS
@@ -402,7 +407,37 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
     __syncthreads();
 }
 
-// T2 candidate enumeration.  Returns false (uniformly) on candidate overflow.
+// Block-wide exclusive scan of v[0..n) in place; v[n] = total.  Each thread
+// scans a contiguous chunk; chunk sums are combined with a wave scan.
+template <int kT, class V>
+__device__ void block_excl_scan(V* v, int n, Scalars& sc) {
+    const int per = (n + kT - 1) / kT;
+    const int b0 = threadIdx.x * per;
+    int loc = 0;
+    for (int i = b0; i < b0 + per && i < n; ++i) loc += v[i];
+    int tot;
+    const int ex = wave_excl_scan(loc, &tot);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) sc.wsum[wv] = tot;
+    __syncthreads();
+    int run = ex;
+    for (int q = 0; q < wv; ++q) run += sc.wsum[q];
+    int total = 0;
+    for (int q = 0; q < kT / kWave; ++q) total += sc.wsum[q];
+    for (int i = b0; i < b0 + per && i < n; ++i) {
+        const int c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) v[n] = total;
+    __syncthreads();
+}
+
+// T2 candidate enumeration, load-balanced over (h0, h2) pairs: (A) every
+// unused h0 gets its azimuth window on plane k+2 (up to two position ranges);
+// (B) a block scan of the window sizes; (C) the pairs are dealt out evenly and
+// each surviving pair searches plane k+1 for its middle hit.  Returns false
+// (uniformly) on candidate overflow.
 template <int kT, class S>
 __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
@@ -421,48 +456,82 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     const uint16_t* lut2 = st.lut(s2);
     auto lower1 = [&](int v) { return lower_lut<S::kLutShift>(lut1, key1, n1, v); };
     auto lower2 = [&](int v) { return lower_lut<S::kLutShift>(lut2, key2, n2, v); };
+    int32_t* pref = st.pref();        // [n0 + 1]
+    int32_t* eb = st.ebuf();          // a0[n0], b0[n0], a1[n0], b1[n0], m1[n0]
+    // (A) windows.  An outward line through h0 passing within D of the axis
+    // keeps every later point within asin(D/r0) of h0's azimuth, and its
+    // radius grows: h2 lies in that wedge, and the predicted middle point lies
+    // between the azimuths of h0 and h2 at radius >= r0, so h1 is within
+    // asin(R_mid/r0) of that arc.
     for (int i0 = threadIdx.x; i0 < n0; i0 += kT) {
-        if (st.U(s0, i0)) continue;
+        int cnt = 0, ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0, m1 = 0;
+        if (!st.U(s0, i0)) {
+            const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
+            const int k0 = st.K(s0, i0);
+            const float r0 = sqrtf(x0 * x0 + y0 * y0);
+            const int mD = disc_keys(p.r_seed, r0);
+            m1 = disc_keys(p.r_mid, r0);
+            int lo[2], hi[2];
+            const int nr = mD < 0 ? (lo[0] = 0, hi[0] = 65535, 1) : key_span(k0, k0, mD, lo, hi);
+            ra0 = lower2(lo[0]);
+            rb0 = lower2(hi[0] + 1);
+            if (nr == 2) {
+                ra1 = lower2(lo[1]);
+                rb1 = lower2(hi[1] + 1);
+            }
+            cnt = (rb0 - ra0) + (rb1 - ra1);
+        }
+        pref[i0] = cnt;
+        eb[i0] = ra0;
+        eb[n0 + i0] = rb0;
+        eb[2 * n0 + i0] = ra1;
+        eb[3 * n0 + i0] = rb1;
+        eb[4 * n0 + i0] = m1;
+    }
+    __syncthreads();
+    // (B)
+    block_excl_scan<kT>(pref, n0, sc);
+    const int np = pref[n0];
+    // (C)
+    for (int pi = threadIdx.x; pi < np; pi += kT) {
+        int lo = 0, hi = n0;  // last i0 with pref[i0] <= pi
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pref[mid] <= pi) lo = mid; else hi = mid;
+        }
+        const int i0 = lo;
+        const int o = pi - pref[i0];
+        const int len0 = eb[n0 + i0] - eb[i0];
+        const int i2 = o < len0 ? eb[i0] + o : eb[2 * n0 + i0] + (o - len0);
+        if (st.U(s2, i2)) continue;
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
+        const float tx = (st.X(s2, i2) - x0) / dz2;
+        const float ty = (st.Y(s2, i2) - y0) / dz2;
+        if (!(fabsf(tx) <= p.t_max && fabsf(ty) <= p.t_max)) continue;
+        if (!(x0 * tx + y0 * ty > 0.0f)) continue;
+        const float cr = x0 * ty - y0 * tx;
+        if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) continue;
+        const float ex = x0 + tx * dz1;
+        const float ey = y0 + ty * dz1;
         const int k0 = st.K(s0, i0);
-        // An outward line through h0 passing within D of the axis keeps every
-        // later point within asin(D/r0) of h0's azimuth, and its radius grows:
-        // h2 lies in that wedge, and the predicted middle point lies between
-        // the azimuths of h0 and h2 at radius >= r0, so h1 is within
-        // asin(R_mid/r0) of that arc.
-        const float r0 = sqrtf(x0 * x0 + y0 * y0);
-        const int mD = disc_keys(p.r_seed, r0);
-        const int m1 = disc_keys(p.r_mid, r0);
-        int lo[2], hi[2];
-        const int nr = mD < 0 ? (lo[0] = 0, hi[0] = 65535, 1) : key_span(k0, k0, mD, lo, hi);
-        visit(lower2, key2, n2, nr, lo, hi, [&](int i2) {
-            if (st.U(s2, i2)) return;
-            const float tx = (st.X(s2, i2) - x0) / dz2;
-            const float ty = (st.Y(s2, i2) - y0) / dz2;
-            if (!(fabsf(tx) <= p.t_max && fabsf(ty) <= p.t_max)) return;
-            if (!(x0 * tx + y0 * ty > 0.0f)) return;
-            const float cr = x0 * ty - y0 * tx;
-            if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) return;
-            const float ex = x0 + tx * dz1;
-            const float ey = y0 + ty * dz1;
-            int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
-            kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
-            int lo1[2], hi1[2];
-            const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
-                                   : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
-            visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) {
-                if (st.U(s1, i1)) return;
-                const float dx = st.X(s1, i1) - ex;
-                const float dy = st.Y(s1, i1) - ey;
-                const float q = dx * dx + dy * dy;
-                if (!(q <= p.s_max)) return;
-                const int c = atomicAdd(&sc.n_cand, 1);
-                if (c < cap) {
-                    st.cq(c) = q;
-                    st.set_cp(c, i0, i1, i2);
-                    st.calive(c) = 1;
-                }
-            });
+        const int m1 = eb[4 * n0 + i0];
+        int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
+        kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
+        int lo1[2], hi1[2];
+        const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
+                               : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
+        visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) {
+            if (st.U(s1, i1)) return;
+            const float dx = st.X(s1, i1) - ex;
+            const float dy = st.Y(s1, i1) - ey;
+            const float q = dx * dx + dy * dy;
+            if (!(q <= p.s_max)) return;
+            const int c = atomicAdd(&sc.n_cand, 1);
+            if (c < cap) {
+                st.cq(c) = q;
+                st.set_cp(c, i0, i1, i2);
+                st.calive(c) = 1;
+            }
         });
     }
     __syncthreads();
@@ -623,9 +692,9 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     }
     __syncthreads();
     const int nw = sc.n_acc;
-    if (t0 + nw > st.cap_tracks() || nw > st.cap_new()) return false;
+    if (t0 + nw > st.cap_tracks()) return false;
     if (nw == 0) return true;
-    st.dbase = t0;
+    uint32_t* rank = wc + nw;
     for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
         wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
@@ -635,8 +704,14 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
         const uint64_t ki = wkey[i];
         int r = 0;
         for (int j = 0; j < nw; ++j) r += wkey[j] < ki ? 1 : 0;
+        rank[i] = (uint32_t)r;
+    }
+    __syncthreads();
+    st.dbase = t0;  // downstream state overlays the winner keys from here on
+    st.dn = nw;
+    for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
-        const int t = t0 + r;
+        const int t = t0 + (int)rank[i];
         const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
         const float x1 = st.X(s1, i1), y1 = st.Y(s1, i1);
@@ -736,11 +811,11 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
     set_event_flag(a.status, e, flag, 1);
 }
 
-template <int kT, int kP, int kTr, int kC, int kN>
+template <int kT, int kP, int kTr, int kC>
 __global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
-    __shared__ Tile<kP, kTr, kC, kN> tile;
+    __shared__ Tile<kP, kTr, kC> tile;
     __shared__ Scalars sc;
-    LdsStore<kP, kTr, kC, kN> st{&tile, &sc, 0};
+    LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
     while (true) {
         if (threadIdx.x == 0) {
             const int i = atomicAdd(a.w.counters + 1, 1);
@@ -867,31 +942,31 @@ __global__ __launch_bounds__(256) void k_accept(FindArgs a) {
     }
 }
 
-template <int kT, int kP, int kTr, int kC, int kN>
+template <int kT, int kP, int kTr, int kC>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, kN>), dim3(grid), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC>), dim3(grid), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int kT, int kP, int kTr, int kC, int kN>
+template <int kT, int kP, int kTr, int kC>
 int occ_lds() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, kN>, kT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess)
         return 1;
     return n;
 }
 
 }  // namespace
 
-// Tile shapes: (plane capacity, tracks, seed candidates per step, new tracks per step).
+// Tile shapes: (plane capacity, tracks, seed candidates per step).
 #define VELO_TILES(X, T)               \
-    X(T, 0, 256, 320, 384, 64)         \
-    X(T, 1, 512, 640, 512, 128)        \
-    X(T, 2, 1024, 1024, 1024, 256)
+    X(T, 0, 256, 320, 384)             \
+    X(T, 1, 512, 640, 640)             \
+    X(T, 2, 1024, 1024, 1024)
 
 hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
-#define VELO_CASE(T, L, P, TR, C, N) \
-    case T * 4 + L: return launch_lds<T, P, TR, C, N>(a, grid, s);
+#define VELO_CASE(T, L, P, TR, C) \
+    case T * 4 + L: return launch_lds<T, P, TR, C>(a, grid, s);
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
@@ -902,8 +977,8 @@ hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, h
 }
 
 int find_blocks_per_cu(int threads, int tile) {
-#define VELO_CASE(T, L, P, TR, C, N) \
-    case T * 4 + L: return occ_lds<T, P, TR, C, N>();
+#define VELO_CASE(T, L, P, TR, C) \
+    case T * 4 + L: return occ_lds<T, P, TR, C>();
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)

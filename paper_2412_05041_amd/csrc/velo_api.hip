@@ -144,6 +144,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
     w.g_dyb = carve<float>(cur, C);
     w.g_tkb = carve<int32_t>(cur, C);
     w.g_twant = carve<int32_t>(cur, C);
+    w.g_enum = carve<int32_t>(cur, 6 * C + 8);
     w.n_large_blocks = 32;
     w.pool_cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 20, C));
     const int64_t pool = w.pool_cap * w.n_large_blocks;
