@@ -61,6 +61,33 @@ def cpu_baseline(batch, cuts, passes):
                        f"event-parallel over {cores} worker processes; {dt:.2f} s wall")
 
 
+def measured_traffic(kernel, launch, workload):
+    """HBM bytes per launch from the committed profiler counter runs, or None
+    when they were taken for another kernel, launch or workload, or when the
+    kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec["kernel"] != kernel or list(rec["launch"]) != list(launch) or h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
+def describe(w, clusters_per_event):
+    """Plain-words description of a synthetic workload."""
+    mult = {"fixed": f"{w.n_tracks} tracks/event",
+            "pv_poisson": f"Poisson({w.pv_mean:g}) PVs x Poisson({w.trk_per_pv:g}) tracks",
+            "lognormal": f"{w.n_tracks} x lognormal(0, {w.ln_sigma:g}) tracks clipped to {list(w.ln_clip)}",
+            "uniform": f"single vertex, U[{w.trk_lo}, {w.trk_hi}] tracks"}[w.tracks]
+    return (f"{w.name}: {w.n_events} events, {mult}, {w.ms_sigma * 1e3:g} mrad MS/plane, "
+            f"noise p={w.noise_p:g} (~{clusters_per_event:.0f} clusters/event), seed {w.seed}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +99,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB 3 times (a known-size kernel that "
+                         "scales HBM byte counters read by a profiler)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -178,8 +208,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{w.name}: {E} events, Poisson(5) PVs x Poisson(40) tracks, 1 mrad MS/plane, "
-                        f"noise p={w.noise_p:g} (~3k clusters/event), seed {w.seed}",
+            "workload": describe(w, n_clu / E),
             "events": E,
             "pixels_per_event": n_pix / E,
             "clusters_per_event": n_clu / E,
@@ -198,12 +227,21 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom, (th, tl), w.name),
+            "alg_bytes": alg[dom],
         },
         "path_hbm_frac": path_bytes / E * value / (HBM_PEAK_GBS * 1e9),
         "stages_ms": stages,
         "cpu_baseline": cpu,
     }
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device=v.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel()
+        del src, dst
     print(json.dumps(out), flush=True)
 
 

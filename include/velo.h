@@ -167,14 +167,16 @@ int velo_pipeline(velo_ctx* ctx, int32_t n_events, const int32_t* d_pix_off, con
 int velo_set_timing(velo_ctx* ctx, int32_t on);
 int velo_last_timing(velo_ctx* ctx, float* h_ms, int32_t n);
 
-/* Launch configuration of the track finder: threads per event (64, 128, 256)
+/* Launch configuration of the track finder: threads per event (64, 128, 256, 512)
  * and LDS tile (0 small, 1 medium, 2 large).  Outputs never depend on it. */
 int velo_set_launch(velo_ctx* ctx, int32_t threads, int32_t tile);
 int velo_get_launch(velo_ctx* ctx, int32_t* threads, int32_t* tile);
 
 /* Times every launch configuration on the given clusters (device inputs, as
  * for velo_find_tracks) and keeps the fastest.  Synchronises the stream.
- * h_ms (nullable) receives the 9 timings, configuration-major. */
+ * h_ms (nullable) receives VELO_N_LAUNCH timings, threads-major (64, 128,
+ * 256, 512) then tile. */
+#define VELO_N_LAUNCH 12
 int velo_autotune(velo_ctx* ctx, int32_t n_events, const int32_t* d_clu_off, const float* d_clu_x,
                   const float* d_clu_y, int32_t reps, float* h_ms, void* stream);
 
@@ -185,7 +187,9 @@ int velo_mlp_set_weights(velo_ctx* ctx, const float* h_master, const float* h_no
 int velo_mlp_get_weights(velo_ctx* ctx, float* h_master, float* h_norm);
 
 /* Features of candidates: d_feat[n][16] BF16 bit patterns, standardised
- * ((f - mean) / sd, FP32, round to nearest even), 10 used, 6 zero. */
+ * ((f - mean) / sd, FP32, round to nearest even), 10 used, 6 zero.  d_feat
+ * may be null when d_feat_f32 is given: then only the raw FP32 features are
+ * written and no normalisation is needed (collecting training data). */
 int velo_features(velo_ctx* ctx, int64_t n_tracks, const int32_t* d_trk_hit_off, const int32_t* d_trk_hit,
                   const uint32_t* d_trk_planes, const float* d_clu_x, const float* d_clu_y,
                   uint16_t* d_feat, float* d_feat_f32 /* nullable [n][10] raw FP32 */, void* stream);

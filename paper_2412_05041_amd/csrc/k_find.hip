@@ -95,6 +95,7 @@ struct Tile {
 struct Scalars {
     int n_tracks, n_cand, n_acc, event, n_pairs;
     int wsum[16];            // per-wave partial sums of block scans
+    float z[kPlanes];        // plane positions (lane-indexed reads stay in LDS)
     int wn[kRing];
     int64_t wg[kRing];       // staged (= cluster) base of the plane in each ring slot
     int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
@@ -308,50 +309,103 @@ __device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf,
 
 // ---------------------------------------------------------------- steps
 
-template <int kT, class S>
-__device__ void load_plane(S& st, const FindArgs& a, int k) {
+// Registers holding the first hits of the next plane, loaded one step ahead so
+// that the global-memory latency overlaps the current step.
+struct Prefetch {
+    float x[2], y[2];
+    int key[2], kprev[2], id[2];
+};
+
+template <int kT, int kPF>
+__device__ __forceinline__ void prefetch_plane(const Scalars& sc, const FindArgs& a, int k, Prefetch& pf) {
+    const int64_t g = sc.cb[k];
+    const int n = (int)(sc.cb[k + 1] - g);
+#pragma unroll
+    for (int r = 0; r < kPF; ++r) {
+        const int i = threadIdx.x + r * kT;
+        if (i < n) {
+            pf.x[r] = a.w.sx[g + i];
+            pf.y[r] = a.w.sy[g + i];
+            pf.key[r] = a.w.skey[g + i];
+            pf.kprev[r] = i ? (int)a.w.skey[g + i - 1] : -1;
+            pf.id[r] = (int)(a.w.sid[g + i] - g);
+        }
+    }
+}
+
+// Bucket index entries owned by position i of a key-sorted plane of n hits:
+// lut[b] = first position whose key bucket is >= b.
+template <int kShift, int kN>
+__device__ __forceinline__ void lut_entries(uint16_t* lut, int i, int n, int key, int kprev) {
+    const int bi = key >> kShift;
+    const int bp = kprev < 0 ? -1 : (kprev >> kShift);
+    for (int b = bp + 1; b <= bi; ++b) lut[b] = (uint16_t)i;
+    if (i == n - 1)
+        for (int b = bi + 1; b <= kN; ++b) lut[b] = (uint16_t)n;
+}
+
+// Plane k into ring slot k % kRing (LDS tile): the used flags of the plane
+// leaving the slot go back to global memory, then hits, flags and bucket
+// index are written by the thread owning each position (one barrier).
+template <int kT, int kPF, class S>
+__device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& pf) {
     Scalars& sc = *st.s;
     const int sl = k % kRing;
-    if constexpr (!S::kLarge) {
-        // hand the used flags of the plane leaving this slot back to global memory
-        if (k + kRing < kPlanes) {
-            const int64_t g = sc.wg[sl];
-            for (int i = threadIdx.x; i < sc.wn[sl]; i += kT) a.w.used[g + i] = st.U(sl, i);
-        }
+    auto* t = st.t;
+    if (k + kRing < kPlanes) {
+        const int64_t og = sc.cb[k + kRing];
+        const int on = (int)(sc.cb[k + kRing + 1] - og);
+        for (int i = threadIdx.x; i < on; i += kT) a.w.used[og + i] = t->wu[sl][i];
     }
-    __syncthreads();
+    const int64_t g = sc.cb[k];
+    const int n = (int)(sc.cb[k + 1] - g);
+    constexpr int kShift = S::kLutShift, kN = S::kLutN;
+    uint16_t* lut = t->lut[sl];
+    auto put = [&](int i, float x, float y, int key, int kprev, int id) {
+        t->wx[sl][i] = x;
+        t->wy[sl][i] = y;
+        t->wk[sl][i] = (uint16_t)key;
+        t->wid[sl][i] = (uint16_t)id;
+        t->wu[sl][i] = 0;
+        t->claim[i] = kIntMax;
+        lut_entries<kShift, kN>(lut, i, n, key, kprev);
+    };
+#pragma unroll
+    for (int r = 0; r < kPF; ++r) {
+        const int i = threadIdx.x + r * kT;
+        if (i < n) put(i, pf.x[r], pf.y[r], pf.key[r], pf.kprev[r], pf.id[r]);
+    }
+    for (int i = threadIdx.x + kPF * kT; i < n; i += kT)
+        put(i, a.w.sx[g + i], a.w.sy[g + i], a.w.skey[g + i], (int)a.w.skey[g + i - 1], (int)(a.w.sid[g + i] - g));
+    if (n == 0)
+        for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
     if (threadIdx.x == 0) {
-        sc.wg[sl] = sc.cb[k];
-        sc.wn[sl] = (int)(sc.cb[k + 1] - sc.cb[k]);
+        sc.wg[sl] = g;
+        sc.wn[sl] = n;
     }
     __syncthreads();
-    const int n = sc.wn[sl];
-    if constexpr (!S::kLarge) {
-        const int64_t g = sc.wg[sl];
-        auto* t = st.t;
-        for (int i = threadIdx.x; i < n; i += kT) {
-            t->wx[sl][i] = a.w.sx[g + i];
-            t->wy[sl][i] = a.w.sy[g + i];
-            t->wk[sl][i] = a.w.skey[g + i];
-            t->wid[sl][i] = (uint16_t)(a.w.sid[g + i] - g);
-            t->wu[sl][i] = 0;
-            t->claim[i] = kIntMax;
-        }
-        __syncthreads();
+}
+
+// Plane k for the large path: only the slot bookkeeping and the bucket index
+// (the hits stay in the global staging arrays).
+template <int kT, class S>
+__device__ void load_plane_global(S& st, int k) {
+    Scalars& sc = *st.s;
+    const int sl = k % kRing;
+    __syncthreads();
+    const int64_t g = sc.cb[k];
+    const int n = (int)(sc.cb[k + 1] - g);
+    if (threadIdx.x == 0) {
+        sc.wg[sl] = g;
+        sc.wn[sl] = n;
     }
-    // bucket index: lut[b] = first position whose key bucket is >= b
+    __syncthreads();
     uint16_t* lut = st.lut(sl);
     constexpr int kShift = S::kLutShift, kN = S::kLutN;
     if (n == 0) {
         for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
     } else {
-        for (int i = threadIdx.x; i < n; i += kT) {
-            const int bi = st.K(sl, i) >> kShift;
-            const int bp = i ? (st.K(sl, i - 1) >> kShift) : -1;
-            for (int b = bp + 1; b <= bi; ++b) lut[b] = (uint16_t)i;
-            if (i == n - 1)
-                for (int b = bi + 1; b <= kN; ++b) lut[b] = (uint16_t)n;
-        }
+        for (int i = threadIdx.x; i < n; i += kT) lut_entries<kShift, kN>(lut, i, n, st.K(sl, i), i ? st.K(sl, i - 1) : -1);
     }
     __syncthreads();
 }
@@ -369,7 +423,7 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
         int want = -1;
         const int kb = st.tkb(t);
         if (n > 0 && kb - k - 1 <= p.max_skip) {
-            const float d = p.z[k] - p.z[kb];
+            const float d = sc.z[k] - sc.z[kb];
             const float ex = st.txb(t) + st.ttx(t) * d;
             const float ey = st.tyb(t) + st.tty(t) * d;
             const uint16_t* lut = st.lut(sl);
@@ -389,7 +443,7 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             st.U(sl, i) = 1;
             const float xh = st.X(sl, i), yh = st.Y(sl, i);
             const int kb = st.tkb(t);
-            const float dz = p.z[kb] - p.z[k];
+            const float dz = sc.z[kb] - sc.z[k];
             st.ttx(t) = (st.txb(t) - xh) / dz;
             st.tty(t) = (st.tyb(t) - yh) / dz;
             st.txb(t) = xh;
@@ -492,14 +546,21 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     // (B)
     block_excl_scan<kT>(pref, n0, sc);
     const int np = pref[n0];
-    // (C)
-    for (int pi = threadIdx.x; pi < np; pi += kT) {
-        int lo = 0, hi = n0;  // last i0 with pref[i0] <= pi
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pref[mid] <= pi) lo = mid; else hi = mid;
+    // (C) each thread takes a contiguous run of pairs: one search for its
+    // first h0, then a forward walk
+    const int per = (np + kT - 1) / kT;
+    const int pb = min(np, (int)threadIdx.x * per), pe = min(np, pb + per);
+    int i0 = 0;
+    if (pb < pe) {
+        int hi = n0;  // last i0 with pref[i0] <= pb
+        while (hi - i0 > 1) {
+            const int mid = (i0 + hi) >> 1;
+            if (pref[mid] <= pb) i0 = mid; else hi = mid;
         }
-        const int i0 = lo;
+    }
+    int nxt = pref[i0 + 1];
+    for (int pi = pb; pi < pe; ++pi) {
+        while (pi >= nxt) nxt = pref[++i0 + 1];
         const int o = pi - pref[i0];
         const int len0 = eb[n0 + i0] - eb[i0];
         const int i2 = o < len0 ? eb[i0] + o : eb[2 * n0 + i0] + (o - len0);
@@ -634,7 +695,7 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
         const int kb = st.dkb(t);
         if (j - kb - 1 <= p.max_skip) {
             active = 1;
-            const float d = p.z[j] - p.z[kb];
+            const float d = st.s->z[j] - st.s->z[kb];
             const float ex = st.dxb(t) + st.dtx(t) * d;
             const float ey = st.dyb(t) + st.dty(t) * d;
             if (n > 0) {
@@ -651,7 +712,7 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
             used(i) = 1;
             const float xh = xf(i), yh = yf(i);
             const int kb = st.dkb(t);
-            const float dz = p.z[kb] - p.z[j];
+            const float dz = st.s->z[kb] - st.s->z[j];
             st.dtx(t) = (st.dxb(t) - xh) / dz;
             st.dty(t) = (st.dyb(t) - yh) / dz;
             st.dxb(t) = xh;
@@ -778,11 +839,22 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
         sc.n_tracks = 0;
         for (int i = 0; i < kRing; ++i) { sc.wn[i] = 0; sc.wg[i] = 0; }
     }
-    for (int k = threadIdx.x; k <= kPlanes; k += kT) sc.cb[k] = a.clu_off[e * kPlanes + k];
+    for (int k = threadIdx.x; k <= kPlanes; k += kT) {
+        sc.cb[k] = a.clu_off[e * kPlanes + k];
+        if (k < kPlanes) sc.z[k] = a.p.z[k];
+    }
     __syncthreads();
     PHASE_T0();
+    constexpr int kPF = kT >= 512 ? 1 : 2;
+    Prefetch pf;
+    if constexpr (!S::kLarge) prefetch_plane<kT, kPF>(sc, a, kPlanes - 1, pf);
     for (int k = kPlanes - 1; k >= 0; --k) {
-        load_plane<kT>(st, a, k);
+        if constexpr (S::kLarge) {
+            load_plane_global<kT>(st, k);
+        } else {
+            load_plane_lds<kT, kPF>(st, a, k, pf);
+            if (k > 0) prefetch_plane<kT, kPF>(sc, a, k - 1, pf);
+        }
         PHASE(0);
         if (sc.n_tracks > 0) forward<kT>(st, a, k);
         PHASE(1);
@@ -812,7 +884,7 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
 }
 
 template <int kT, int kP, int kTr, int kC>
-__global__ __launch_bounds__(kT) void k_find_lds(FindArgs a) {
+__global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) {
     __shared__ Tile<kP, kTr, kC> tile;
     __shared__ Scalars sc;
     LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
@@ -971,6 +1043,7 @@ hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, h
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
         VELO_TILES(VELO_CASE, 256)
+        VELO_TILES(VELO_CASE, 512)
         default: return hipErrorInvalidValue;
     }
 #undef VELO_CASE
@@ -983,6 +1056,7 @@ int find_blocks_per_cu(int threads, int tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
         VELO_TILES(VELO_CASE, 256)
+        VELO_TILES(VELO_CASE, 512)
         default: return 1;
     }
 #undef VELO_CASE

@@ -363,6 +363,7 @@ __global__ __launch_bounds__(256) void k_features(Params p, const float* norm, i
     raw_features(f, p.sigma, raw);
     if (feat32)
         for (int i = 0; i < 10; ++i) feat32[t * 10 + i] = raw[i];
+    if (!feat) return;
     uint16_t fb[16];
     std_features(raw, norm, fb);
     uint4* out = reinterpret_cast<uint4*>(feat + t * 16);

@@ -304,7 +304,8 @@ int velo_set_validate(velo_ctx* c, int32_t on) {
 
 int velo_set_launch(velo_ctx* c, int32_t threads, int32_t tile) {
     if (!c) return fail(VELO_ERR_ARG, "null context");
-    if (threads != 64 && threads != 128 && threads != 256) return fail(VELO_ERR_ARG, "threads must be 64/128/256");
+    if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
+        return fail(VELO_ERR_ARG, "threads must be 64/128/256/512");
     if (tile < 0 || tile > 2) return fail(VELO_ERR_ARG, "tile must be 0..2");
     c->threads = threads;
     c->tile = tile;
@@ -505,7 +506,7 @@ int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* c
     if (E <= 0 || !clu_off || !clu_x || !clu_y || reps <= 0) return fail(VELO_ERR_ARG, "bad arguments");
     if (int rc = check_reserved(c, E, 0)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int threads[3] = {64, 128, 256};
+    const int threads[4] = {64, 128, 256, 512};
     float best = 1e30f;
     int bt = c->threads, bl = c->tile;
     hipEvent_t e0, e1;
@@ -517,7 +518,7 @@ int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* c
     StageArgs sa{E * kPlanes, clu_off, clu_x, clu_y, c->w};
     HIP_OK(launch_stage(sa, s));
     int idx = 0;
-    for (int ti = 0; ti < 3; ++ti) {
+    for (int ti = 0; ti < 4; ++ti) {
         for (int tl = 0; tl < 3; ++tl, ++idx) {
             c->threads = threads[ti];
             c->tile = tl;
@@ -613,8 +614,9 @@ int velo_features(velo_ctx* c, int64_t n, const int32_t* trk_hit_off, const int3
                   float* feat32, void* stream) {
     if (!c || n < 0) return fail(VELO_ERR_ARG, "bad arguments");
     if (n == 0) return VELO_OK;
-    if (!trk_hit_off || !trk_hit || !trk_planes || !clu_x || !clu_y || !feat) return fail(VELO_ERR_ARG, "null argument");
-    if (!c->mlp.has_weights) return fail(VELO_ERR_ARG, "normalisation not set (velo_mlp_set_weights)");
+    if (!trk_hit_off || !trk_hit || !trk_planes || !clu_x || !clu_y || (!feat && !feat32))
+        return fail(VELO_ERR_ARG, "null argument");
+    if (feat && !c->mlp.has_weights) return fail(VELO_ERR_ARG, "normalisation not set (velo_mlp_set_weights)");
     HIP_OK(launch_features(c->p, c->mlp.d_norm, n, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, feat, feat32,
                            (hipStream_t)stream));
     return VELO_OK;

@@ -57,7 +57,8 @@ def candidates(v: velo.Velo, batch: gen.Batch, with_labels=True):
     n_clu = int(c["clu_off"][-1].item())
     t = v.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], n_clu=n_clu, emit_rejected=True)
     T = int(t["trk_off"][-1].item())
-    feat, raw = v.features(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], T, raw=True)
+    raw = v.features(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], T, raw=True,
+                     standardised=False)
     out = dict(raw=raw[:T].cpu().numpy(), plain=(t["trk_flags"][:T].cpu().numpy() & velo.TRK_PLAIN_ACCEPT) != 0)
     if with_labels:
         H = int(t["trk_hit_off"][T].item())
@@ -67,7 +68,7 @@ def candidates(v: velo.Velo, batch: gen.Batch, with_labels=True):
     return out
 
 
-def collect(v: velo.Velo, workload: gen.Workload, n_target: int, chunk_events: int = 20000):
+def collect(v: velo.Velo, workload: gen.Workload, n_target: int, chunk_events: int = 20000, log=None):
     """Candidates from successive generator batches until n_target are collected."""
     raws, labs, plains = [], [], []
     n, i = 0, 0
@@ -80,6 +81,8 @@ def collect(v: velo.Velo, workload: gen.Workload, n_target: int, chunk_events: i
         plains.append(d["plain"])
         n += len(d["label"])
         i += 1
+        if log:
+            log(f"chunk {i}: {n} candidates")
     return np.concatenate(raws)[:n_target], np.concatenate(labs)[:n_target], np.concatenate(plains)[:n_target]
 
 

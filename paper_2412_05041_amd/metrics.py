@@ -27,13 +27,16 @@ def cluster_truth(pix_clu, pix_mc, n_clu):
     mc = np.asarray(pix_mc, np.int64)
     if pix_clu.size == 0:
         return np.full(n_clu, -1, np.int64)
-    # rank: real ids ascending, noise last
-    pri = np.where(mc < 0, np.int64(1) << 40, mc)
-    key = pix_clu * (np.int64(1) << 41) + pri
-    u, cnt = np.unique(key, return_counts=True)
-    clu = u >> 41
-    pr = u & ((np.int64(1) << 41) - 1)
-    noise = pr == (np.int64(1) << 40)
+    # distinct (cluster, id) pairs with their pixel counts; noise ranks last
+    noise_px = mc < 0
+    pri = np.where(noise_px, mc.max(initial=0) + 1, mc)
+    o = np.lexsort((pri, pix_clu))
+    c_s, p_s = pix_clu[o], pri[o]
+    new = np.ones(c_s.size, bool)
+    new[1:] = (c_s[1:] != c_s[:-1]) | (p_s[1:] != p_s[:-1])
+    start = np.flatnonzero(new)
+    cnt = np.diff(np.append(start, c_s.size))
+    clu, pr, noise = c_s[start], p_s[start], noise_px[o][start]
     # order per cluster: real before noise, more pixels first, lower id first
     order = np.lexsort((pr, -cnt, noise, clu))
     clu_o = clu[order]

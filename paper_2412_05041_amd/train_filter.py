@@ -58,7 +58,7 @@ def main():
     zs = gen.plane_z()
     v = velo.Velo(zs, loose)
     t0 = time.time()
-    raw, lab, plain = learned.collect(v, gen.WORKLOADS["learned_train"], args.candidates)
+    raw, lab, plain = learned.collect(v, gen.WORKLOADS["learned_train"], args.candidates, log=log)
     log(f"collected {len(lab)} candidates ({lab.mean():.4%} ghosts) in {time.time() - t0:.1f}s")
     n_val = len(lab) // 10
     norm = learned.normalisation(raw[:-n_val])

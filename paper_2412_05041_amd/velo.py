@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvelo.so")
 
 N_PLANES = 26
+N_LAUNCH = 12  # finder launch configurations timed by the autotuner
 N_PARAM = 1441
 STATUS_HDR = 8
 EV_OVERFLOW, EV_BAD_INPUT, EV_LARGE_PATH, EV_FALLBACK = 1, 2, 4, 8
@@ -229,21 +230,21 @@ class Velo:
         return bufs
 
     def autotune(self, clu_off, clu_x, clu_y, reps=3, cache=None, key=None):
-        """Times the 9 finder launch configurations on these clusters and keeps
+        """Times the N_LAUNCH finder launch configurations on these clusters and keeps
         the fastest.  With cache (a JSON file) and key (a workload label), a
         stored choice for (device arch, CU count, key) is reused instead."""
         ident = None
         if cache is not None and key is not None:
             import json
             p = torch.cuda.get_device_properties(self.device)
-            ident = f"{getattr(p, 'gcnArchName', p.name)}|{p.multi_processor_count}|{key}"
+            ident = f"{getattr(p, 'gcnArchName', p.name)}|{p.multi_processor_count}|{N_LAUNCH}|{key}"
             table = json.load(open(cache)) if os.path.exists(cache) else {}
             if ident in table:
                 th, tl = table[ident]["launch"]
                 self.set_launch(th, tl)
                 return table[ident]["ms"], (th, tl)
         E = (clu_off.numel() - 1) // N_PLANES
-        ms = (C.c_float * 9)()
+        ms = (C.c_float * N_LAUNCH)()
         _check(lib().velo_autotune(self.h, E, _ptr(clu_off), _ptr(clu_x), _ptr(clu_y), reps, ms, _stream()))
         res = (list(ms), self.get_launch())
         if ident is not None:
@@ -284,11 +285,15 @@ class Velo:
         _check(lib().velo_mlp_get_weights(self.h, m.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
         return m, n
 
-    def features(self, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, n_tracks, raw=False):
-        feat = torch.zeros((max(n_tracks, 1), 16), dtype=torch.int16, device=self.device)
+    def features(self, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, n_tracks, raw=False, standardised=True):
+        """BF16 standardised features (needs the normalisation), and with raw=True
+        also the raw FP32 features; standardised=False returns the raw ones only."""
+        feat = torch.zeros((max(n_tracks, 1), 16), dtype=torch.int16, device=self.device) if standardised else None
         f32 = torch.zeros((max(n_tracks, 1), 10), dtype=torch.float32, device=self.device) if raw else None
         _check(lib().velo_features(self.h, n_tracks, _ptr(trk_hit_off), _ptr(trk_hit), _ptr(trk_planes), _ptr(clu_x),
                                    _ptr(clu_y), _ptr(feat), _ptr(f32), _stream()))
+        if not standardised:
+            return f32
         return (feat, f32) if raw else feat
 
     def standardize(self, raw, n=None):

@@ -81,6 +81,11 @@ def test_features_bit_exact_and_standardisation(velo_mod):
     assert np.array_equal(np_(feat, T).view(np.uint16), ref)
     s = v.standardize(dev(t["trk_feat"]), T)
     assert np.array_equal(np_(s, T).view(np.uint16), ref)
+    # raw features alone need no normalisation
+    v0 = velo_mod.Velo(gen.plane_z(), cut)
+    raw0 = v0.features(dev(t["trk_hit_off"]), dev(t["trk_hit"]), dev(t["trk_planes"].view(np.int32)),
+                       dev(c["clu_x"]), dev(c["clu_y"]), T, raw=True, standardised=False)
+    assert np.array_equal(np_(raw0, T).view(np.int32), t["trk_feat"].view(np.int32))
 
 
 @pytest.mark.parametrize("n", [65536, 10007])

@@ -38,3 +38,27 @@ def test_reconstructible_needs_three_planes():
     r = metrics.eff_ghost(b, pix_clu, clu_off, np.array([0, 1]), np.array([0, 3]), np.array([0, 2, 4]))
     assert r["n_reconstructible"] == 1
     assert r["efficiency"] == 1.0 and r["ghost_rate"] == 0.0
+
+
+def brute_cluster_truth(pix_clu, pix_mc, n_clu):
+    out = np.full(n_clu, -1, np.int64)
+    for c in np.unique(pix_clu):
+        ids = pix_mc[pix_clu == c]
+        real = ids[ids >= 0]
+        if real.size:
+            v, n = np.unique(real, return_counts=True)
+            out[c] = v[np.argmax(n)]  # argmax takes the first (lowest id) among equal counts
+    return out
+
+
+def test_cluster_truth_large_indices_match_brute_force():
+    # cluster indices above 2**22 (a 20000-event batch has ~8.6M clusters)
+    rng = np.random.default_rng(5)
+    base = (1 << 23) + 12345
+    pix_clu = base + rng.integers(0, 400, 3000)
+    pix_mc = rng.integers(-1, 6, 3000)
+    n_clu = base + 400
+    got = metrics.cluster_truth(pix_clu, pix_mc, n_clu)
+    ref = brute_cluster_truth(pix_clu, pix_mc, n_clu)
+    assert np.array_equal(got[base:], ref[base:])
+    assert np.all(got[:base] == -1)
