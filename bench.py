@@ -37,7 +37,7 @@ def _oracle_chunk(args):
     return int(pix_off.size - 1) // 26
 
 
-def cpu_baseline(batch, cuts, passes):
+def cpu_baseline(batch, cuts, passes, min_wall):
     import multiprocessing as mp
 
     import oracle
@@ -52,13 +52,20 @@ def cpu_baseline(batch, cuts, passes):
     with ctx.Pool(cores) as pool:
         pool.map(_oracle_chunk, chunks[:cores])  # warm the workers
         t0 = time.perf_counter()
-        n = 0
-        for _ in range(passes):
+        n = done = 0
+        while done < passes or time.perf_counter() - t0 < min_wall:
             n += sum(pool.map(_oracle_chunk, chunks))
+            done += 1
         dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="events/s", cores=cores, kind="oracle",
-                sample=f"all {batch.n_events} events of the benchmark batch x {passes} passes, "
-                       f"event-parallel over {cores} worker processes; {dt:.2f} s wall")
+                sample=f"all {batch.n_events} events of the benchmark batch x {done} passes "
+                       f"(cluster + find + FP64 fit), event-parallel over {cores} worker processes; "
+                       f"{dt:.2f} s wall, ~{dt * cores:.0f} s of CPU work")
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(kernel, launch, workload):
@@ -94,8 +101,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["plain", "learned"], default="plain")
+    ap.add_argument("--path", choices=["fused", "three-call"], default="fused",
+                    help="fused: velo_pipeline (one replayed HIP graph); three-call: velo_cluster, "
+                         "velo_find_tracks, velo_fit launched eagerly")
     ap.add_argument("--workload", default="nominal")
-    ap.add_argument("--cpu-passes", type=int, default=3)
+    ap.add_argument("--cpu-passes", type=int, default=1, help="minimum passes of the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=1.5, help="minimum wall time of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
@@ -118,10 +129,12 @@ def main():
     cuts = json.load(open(os.path.join(cfg, "cuts_ms.json" if w.ms_sigma > 0 else "cuts_default.json")))
     batch = gen.generate(w)
     E = batch.n_events
+    log(f"generated {E} {w.name} events, {batch.n_pix} pixels")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, cuts, args.cpu_passes)
+        cpu = cpu_baseline(batch, cuts, args.cpu_passes, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.0f} events/s on {cpu['cores']} cores")
 
     import torch
 
@@ -148,17 +161,24 @@ def main():
         tune_ms = None
     bufs = v.pipeline_buffers(E, batch.n_pix)
     torch.cuda.synchronize()
+    log(f"launch {v.get_launch()}, warm-up")
 
+    step = v.pipeline if args.path == "fused" else v.three_call
     for _ in range(args.warmup):
-        v.pipeline(off, ids, bufs)
+        step(off, ids, bufs)
     torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        v.pipeline(off, ids, bufs)
+        step(off, ids, bufs)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * E / dt
     st = v.read_status(bufs["status"])
+    if args.path == "three-call":
+        stc = v.read_status(bufs["status_clu"])
+        st[0] = max(st[0], stc[0])
+        st[1] = stc[1]
     if st[0] != 0:
         print(f"status error: {st[:8]}", file=sys.stderr)
         sys.exit(1)
@@ -214,6 +234,7 @@ def main():
             "clusters_per_event": n_clu / E,
             "tracks_per_event": T / E,
             "mode": args.mode,
+            "path": args.path,
             "launch": {"threads_per_event": th, "tile": tl},
             "autotune_ms": tune_ms,
         },

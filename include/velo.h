@@ -31,7 +31,10 @@
  *       d_status[1..4]          required clusters, tracks, track hits, pixels
  *       d_status[5]             events processed by the large-event path
  *       d_status[6]             tracks decided by the plain-cut fallback
- *       d_status[7]             reserved
+ *       d_status[7]             largest seed-candidate count of one plane step
+ *                               on the large-event path (its pool per workgroup
+ *                               is min(2^23, max(2^16, 16 * max_clusters /
+ *                               max_events)) entries; beyond it: overflow)
  *       d_status[8 + e]         flags of event e (VELO_EV_*)
  *     so d_status holds VELO_STATUS_WORDS(n_events) int32.  On overflow every
  *     offset array is still complete and exact; element arrays are written only

@@ -9,6 +9,13 @@ namespace velo {
 constexpr int kPlanes = 26;
 constexpr int kSide = 1454;
 constexpr int kStatusHdr = 8;
+// Square grid over the sensor plane for disc searches on crowded planes:
+// 0.5 mm cells over [-40, 40] mm in x and y.
+constexpr int kGridN = 160;
+constexpr int kCells = kGridN * kGridN;
+constexpr float kGridInv = 2.0f;
+constexpr float kGridOrg = 40.0f;
+constexpr int64_t kCellWords = (int64_t)26 * (kCells + 1) + kCells;  // per workgroup
 constexpr int kWave = 64;
 constexpr int kKeyBits = 16;          // azimuth key resolution
 constexpr int kBuckets = 1024;        // counting-sort buckets of large segments (top 10 key bits)
@@ -30,7 +37,7 @@ struct Params {
 enum : int { EV_OVERFLOW = 1, EV_BAD_INPUT = 2, EV_LARGE = 4, EV_FALLBACK = 8 };
 enum : int { TRK_PLAIN = 1, TRK_LEARNED = 2, TRK_FALLBACK = 4, TRK_ACCEPT = 8 };
 enum : int { ST_SEVERITY = 0, ST_NCLU = 1, ST_NTRK = 2, ST_NHIT = 3, ST_NPIX = 4, ST_NLARGE = 5,
-             ST_NFALLBACK = 6 };
+             ST_NFALLBACK = 6, ST_MAXCAND = 7 };
 
 // Device workspace (allocated by velo_reserve).  Per-cluster arrays are indexed
 // by global cluster index; per-candidate arrays by candidate slot, where the
@@ -42,6 +49,13 @@ struct Work {
     uint16_t* skey;
     int32_t* sid;
     uint8_t* used;        // per staged position: hit taken
+    // large-event path: each plane's hits again in grid-cell order (x, y and
+    // the staged position), and per workgroup the cell starts of all planes
+    // of its current event followed by one plane's fill counters
+    float* g_gx;
+    float* g_gy;
+    int32_t* g_gpos;
+    int32_t* g_cell;
     // candidates
     int32_t* chits;       // [slot][26] global cluster index of the hit on each plane
     uint32_t* cmask;      // planes bitmask

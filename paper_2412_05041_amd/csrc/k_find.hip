@@ -197,6 +197,8 @@ struct GlobalStore {
     __device__ int cap_tracks() const { return cap_t; }
     __device__ int cap_cand() const { return (int)w->pool_cap; }
     int dbase = 0, dn = 0;
+    int32_t* cell = nullptr;  // this workgroup's grid cell starts (plane-major)
+    __device__ const int32_t* cells(int j) const { return cell + (int64_t)j * (kCells + 1); }
     __device__ int32_t* pref() { return w->g_enum + 6 * s->cb[seed_k]; }
     __device__ int32_t* ebuf() { return w->g_enum + 6 * s->cb[seed_k] + s->cb[seed_k + 1] - s->cb[seed_k] + 1; }
     static constexpr int kLutN = kLutLarge;
@@ -231,6 +233,25 @@ __device__ __forceinline__ int point_window(float ex, float ey, float R, int* lo
     if (!(r > R * 1.001f + 1e-3f)) { lo[0] = 0; hi[0] = 65535; return 1; }
     const float half = asinf(R / r) * 1.0001f + 2e-4f;
     return key_ranges(atan2f(ey, ex), half, lo, hi);
+}
+
+// Grid cell (one axis) of a coordinate; monotone in v, clamped to the grid.
+__device__ __forceinline__ int grid_cell1(float v) {
+    const float c = floorf((v + kGridOrg) * kGridInv);
+    return (int)fminf(fmaxf(c, 0.0f), (float)(kGridN - 1));
+}
+
+// Visits every cell-order position whose cell meets the square around the
+// disc (c, R); a margin of 1e-3 mm keeps the FP32 bounds outside the disc.
+template <class F>
+__device__ __forceinline__ void grid_visit(const int32_t* cs, float cx, float cy, float R, F f) {
+    const float rm = R + 1e-3f;
+    const int ix0 = grid_cell1(cx - rm), ix1 = grid_cell1(cx + rm);
+    const int iy0 = grid_cell1(cy - rm), iy1 = grid_cell1(cy + rm);
+    for (int iy = iy0; iy <= iy1; ++iy) {
+        const int e = cs[iy * kGridN + ix1 + 1];
+        for (int q = cs[iy * kGridN + ix0]; q < e; ++q) f(q);
+    }
 }
 
 template <class KF>
@@ -307,7 +328,51 @@ __device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf,
     return want;
 }
 
+// best_hit on a plane of the large-event path through its grid (same rule).
+__device__ __forceinline__ int best_hit_grid(const Work& w, const int32_t* cs, int64_t g, float ex, float ey,
+                                             const Params& p) {
+    float bq = 0.0f;
+    int bid = kIntMax, want = -1;
+    grid_visit(cs, ex, ey, p.r_ext, [&](int q0) {
+        const int i = w.g_gpos[g + q0];
+        if (w.used[g + i]) return;
+        const float dx = w.g_gx[g + q0] - ex;
+        const float dy = w.g_gy[g + q0] - ey;
+        const float q = dx * dx + dy * dy;
+        if (!(q <= p.e_max)) return;
+        const int id = (int)(w.sid[g + i] - g);
+        if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+    });
+    return want;
+}
+
 // ---------------------------------------------------------------- steps
+
+// Block-wide exclusive scan of v[0..n) in place; v[n] = total.  Each thread
+// scans a contiguous chunk; chunk sums are combined with a wave scan.
+template <int kT, class V>
+__device__ void block_excl_scan(V* v, int n, Scalars& sc) {
+    const int per = (n + kT - 1) / kT;
+    const int b0 = threadIdx.x * per;
+    int loc = 0;
+    for (int i = b0; i < b0 + per && i < n; ++i) loc += v[i];
+    int tot;
+    const int ex = wave_excl_scan(loc, &tot);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) sc.wsum[wv] = tot;
+    __syncthreads();
+    int run = ex;
+    for (int q = 0; q < wv; ++q) run += sc.wsum[q];
+    int total = 0;
+    for (int q = 0; q < kT / kWave; ++q) total += sc.wsum[q];
+    for (int i = b0; i < b0 + per && i < n; ++i) {
+        const int c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) v[n] = total;
+    __syncthreads();
+}
 
 // Registers holding the first hits of the next plane, loaded one step ahead so
 // that the global-memory latency overlaps the current step.
@@ -386,11 +451,14 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
     __syncthreads();
 }
 
-// Plane k for the large path: only the slot bookkeeping and the bucket index
-// (the hits stay in the global staging arrays).
+// Plane k for the large path: slot bookkeeping, the bucket index, and the
+// plane's grid (a counting sort of its hits by cell; the order inside a cell
+// is whatever the atomics give -- every search takes a minimum or collects a
+// set, so results never depend on it).  The hits stay in global memory.
 template <int kT, class S>
 __device__ void load_plane_global(S& st, int k) {
     Scalars& sc = *st.s;
+    const Work& w = *st.w;
     const int sl = k % kRing;
     __syncthreads();
     const int64_t g = sc.cb[k];
@@ -399,13 +467,32 @@ __device__ void load_plane_global(S& st, int k) {
         sc.wg[sl] = g;
         sc.wn[sl] = n;
     }
+    int32_t* cs = st.cell + (int64_t)k * (kCells + 1);
+    int32_t* fill = st.cell + (int64_t)kPlanes * (kCells + 1);
+    for (int c = threadIdx.x; c < kCells; c += kT) {
+        cs[c] = 0;
+        fill[c] = 0;
+    }
     __syncthreads();
     uint16_t* lut = st.lut(sl);
     constexpr int kShift = S::kLutShift, kN = S::kLutN;
     if (n == 0) {
         for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
     } else {
-        for (int i = threadIdx.x; i < n; i += kT) lut_entries<kShift, kN>(lut, i, n, st.K(sl, i), i ? st.K(sl, i - 1) : -1);
+        for (int i = threadIdx.x; i < n; i += kT) {
+            lut_entries<kShift, kN>(lut, i, n, st.K(sl, i), i ? st.K(sl, i - 1) : -1);
+            atomicAdd(cs + grid_cell1(w.sy[g + i]) * kGridN + grid_cell1(w.sx[g + i]), 1);
+        }
+    }
+    __syncthreads();
+    block_excl_scan<kT>(cs, kCells, sc);
+    for (int i = threadIdx.x; i < n; i += kT) {
+        const float x = w.sx[g + i], y = w.sy[g + i];
+        const int c = grid_cell1(y) * kGridN + grid_cell1(x);
+        const int q = cs[c] + atomicAdd(fill + c, 1);
+        w.g_gx[g + q] = x;
+        w.g_gy[g + q] = y;
+        w.g_gpos[g + q] = i;
     }
     __syncthreads();
 }
@@ -426,12 +513,16 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             const float d = sc.z[k] - sc.z[kb];
             const float ex = st.txb(t) + st.ttx(t) * d;
             const float ey = st.tyb(t) + st.tty(t) * d;
-            const uint16_t* lut = st.lut(sl);
-            auto key = [&](int i) { return st.K(sl, i); };
-            want = best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, n, v); }, key,
-                            [&](int i) { return st.U(sl, i); },
-                            [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
-                            [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
+            if constexpr (S::kLarge) {
+                want = best_hit_grid(a.w, st.cells(k), sc.wg[sl], ex, ey, p);
+            } else {
+                const uint16_t* lut = st.lut(sl);
+                auto key = [&](int i) { return st.K(sl, i); };
+                want = best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, n, v); }, key,
+                                [&](int i) { return st.U(sl, i); },
+                                [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
+                                [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
+            }
             if (want >= 0) atomicMin(claim + want, t);
         }
         st.twant(t) = want;
@@ -458,32 +549,6 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
         const int i = st.twant(t);
         if (i >= 0) claim[i] = kIntMax;
     }
-    __syncthreads();
-}
-
-// Block-wide exclusive scan of v[0..n) in place; v[n] = total.  Each thread
-// scans a contiguous chunk; chunk sums are combined with a wave scan.
-template <int kT, class V>
-__device__ void block_excl_scan(V* v, int n, Scalars& sc) {
-    const int per = (n + kT - 1) / kT;
-    const int b0 = threadIdx.x * per;
-    int loc = 0;
-    for (int i = b0; i < b0 + per && i < n; ++i) loc += v[i];
-    int tot;
-    const int ex = wave_excl_scan(loc, &tot);
-    const int wv = threadIdx.x / kWave;
-    if ((threadIdx.x % kWave) == 0) sc.wsum[wv] = tot;
-    __syncthreads();
-    int run = ex;
-    for (int q = 0; q < wv; ++q) run += sc.wsum[q];
-    int total = 0;
-    for (int q = 0; q < kT / kWave; ++q) total += sc.wsum[q];
-    for (int i = b0; i < b0 + per && i < n; ++i) {
-        const int c = v[i];
-        v[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == 0) v[n] = total;
     __syncthreads();
 }
 
@@ -574,17 +639,10 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
         if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) continue;
         const float ex = x0 + tx * dz1;
         const float ey = y0 + ty * dz1;
-        const int k0 = st.K(s0, i0);
-        const int m1 = eb[4 * n0 + i0];
-        int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
-        kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
-        int lo1[2], hi1[2];
-        const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
-                               : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
-        visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) {
+        auto try_mid = [&](int i1, float x1, float y1) {
             if (st.U(s1, i1)) return;
-            const float dx = st.X(s1, i1) - ex;
-            const float dy = st.Y(s1, i1) - ey;
+            const float dx = x1 - ex;
+            const float dy = y1 - ey;
             const float q = dx * dx + dy * dy;
             if (!(q <= p.s_max)) return;
             const int c = atomicAdd(&sc.n_cand, 1);
@@ -593,9 +651,27 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
                 st.set_cp(c, i0, i1, i2);
                 st.calive(c) = 1;
             }
-        });
+        };
+        if constexpr (S::kLarge) {
+            // crowded planes: the disc of radius R_mid around the prediction
+            const int64_t g1 = sc.wg[s1];
+            grid_visit(st.cells(k + 1), ex, ey, p.r_mid,
+                       [&](int q1) { try_mid(a.w.g_gpos[g1 + q1], a.w.g_gx[g1 + q1], a.w.g_gy[g1 + q1]); });
+        } else {
+            const int k0 = st.K(s0, i0);
+            const int m1 = eb[4 * n0 + i0];
+            int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
+            kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
+            int lo1[2], hi1[2];
+            const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
+                                   : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
+            visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) { try_mid(i1, st.X(s1, i1), st.Y(s1, i1)); });
+        }
     }
     __syncthreads();
+    if constexpr (S::kLarge) {
+        if (threadIdx.x == 0 && a.status) atomicMax(a.status + ST_MAXCAND, sc.n_cand);
+    }
     return sc.n_cand <= cap;
 }
 
@@ -699,7 +775,8 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
             const float ex = st.dxb(t) + st.dtx(t) * d;
             const float ey = st.dyb(t) + st.dty(t) * d;
             if (n > 0) {
-                want = best_hit(lower, key, used, xf, yf, idf, n, ex, ey, p);
+                if constexpr (S::kLarge) want = best_hit_grid(a.w, st.cells(j), gbase, ex, ey, p);
+                else want = best_hit(lower, key, used, xf, yf, idf, n, ex, ey, p);
                 if (want >= 0) atomicMin(claimT + want, t);
             }
         }
@@ -925,6 +1002,7 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
     GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
     st.luts = luts;
+    st.cell = a.w.g_cell + (int64_t)blockIdx.x * kCellWords;
     const int n_large = a.w.counters[2];
     while (true) {
         if (threadIdx.x == 0) {

@@ -108,7 +108,7 @@ T* carve(char*& cur, int64_t n) {
     return p;
 }
 
-size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
+size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
     char* cur = base;
     const int64_t PX = std::max(P, C);
     w.sx = carve<float>(cur, C);
@@ -145,8 +145,18 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C) {
     w.g_tkb = carve<int32_t>(cur, C);
     w.g_twant = carve<int32_t>(cur, C);
     w.g_enum = carve<int32_t>(cur, 6 * C + 8);
-    w.n_large_blocks = 32;
-    w.pool_cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 20, C));
+    w.g_gx = carve<float>(cur, C);
+    w.g_gy = carve<float>(cur, C);
+    w.g_gpos = carve<int32_t>(cur, C);
+    // global-memory finder: each workgroup owns a seed-candidate pool for one
+    // plane step of its current event, sized from the mean event (16 entries
+    // per cluster: noise-dominated planes give ~2 candidates per hit pair
+    // passing the pair cuts); as many workgroups as a pool budget of 8 entries
+    // per cluster allows (at most 2 per CU, at least 1)
+    w.pool_cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 23, 16 * (C / std::max(E, 1))));
+    const int64_t budget = std::max<int64_t>(1 << 20, std::min<int64_t>(int64_t(1) << 29, 8 * C));
+    w.n_large_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2 * std::max(n_cu, 1), budget / w.pool_cap));
+    w.g_cell = carve<int32_t>(cur, kCellWords * w.n_large_blocks);
     const int64_t pool = w.pool_cap * w.n_large_blocks;
     w.p_q = carve<float>(cur, pool);
     w.p_h = carve<int32_t>(cur, pool * 3);
@@ -336,11 +346,11 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
     }
     Work w{};
     const size_t bytes = layout(w, nullptr, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
-                                std::max<int64_t>(max_clusters, 1));
+                                std::max<int64_t>(max_clusters, 1), c->n_cu);
     void* base = nullptr;
     HIP_OK(hipMalloc(&base, bytes));
     layout(w, (char*)base, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
-           std::max<int64_t>(max_clusters, 1));
+           std::max<int64_t>(max_clusters, 1), c->n_cu);
     c->w = w;
     c->ws = base;
     c->ws_bytes = bytes;

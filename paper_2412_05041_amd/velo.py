@@ -219,6 +219,28 @@ class Velo:
                     par=torch.zeros((max(trk_cap, 1), 8), dtype=torch.float32, device=self.device),
                     trk_cap=trk_cap, hit_cap=hit_cap, status=self.status_buffer(n_events))
 
+    def three_call(self, pix_off, pix_id, bufs):
+        """velo_cluster, velo_find_tracks and velo_fit one after the other on the
+        buffers of pipeline_buffers (no host synchronisation; the fit reads its
+        track count from trk_off[E] on the device).  Same outputs as pipeline;
+        the clustering status goes to bufs["status_clu"]."""
+        E = (pix_off.numel() - 1) // N_PLANES
+        if "status_clu" not in bufs:  # each call resets the status words it is given
+            bufs["status_clu"] = self.status_buffer(E)
+        st = _ptr(bufs["status"])
+        _check(lib().velo_cluster(self.h, E, _ptr(pix_off), _ptr(pix_id), _ptr(bufs["pix_clu"]),
+                                  _ptr(bufs["clu_off"]), _ptr(bufs["clu_x"]), _ptr(bufs["clu_y"]), None,
+                                  bufs["clu_cap"], _ptr(bufs["status_clu"]), _stream()))
+        _check(lib().velo_find_tracks(self.h, E, _ptr(bufs["clu_off"]), _ptr(bufs["clu_x"]), _ptr(bufs["clu_y"]),
+                                      _ptr(bufs["trk_off"]), _ptr(bufs["trk_hit_off"]), _ptr(bufs["trk_hit"]),
+                                      _ptr(bufs["trk_planes"]), _ptr(bufs["trk_flags"]), _ptr(bufs["trk_logit"]),
+                                      bufs["trk_cap"], bufs["hit_cap"], 0, st, _stream()))
+        n_trk = C.c_void_p(bufs["trk_off"].data_ptr() + 4 * E)
+        _check(lib().velo_fit(self.h, bufs["trk_cap"], n_trk, _ptr(bufs["trk_hit_off"]), _ptr(bufs["trk_hit"]),
+                              _ptr(bufs["trk_planes"]), _ptr(bufs["clu_x"]), _ptr(bufs["clu_y"]), _ptr(bufs["par"]),
+                              _stream()))
+        return bufs
+
     def pipeline(self, pix_off, pix_id, bufs):
         E = (pix_off.numel() - 1) // N_PLANES
         b = bufs

@@ -97,6 +97,28 @@ def test_pipeline_matches_oracle_and_replays(velo_mod, name, n, cutname):
             assert np.array_equal(np_(bufs["par"], T), first)
 
 
+@pytest.mark.parametrize("name,n,cutname", WORKLOADS[:2])
+def test_three_calls_on_pipeline_buffers(velo_mod, name, n, cutname):
+    """velo_cluster -> velo_find_tracks -> velo_fit on the pipeline's buffers,
+    with the fit's track count read on the device: the oracle's outputs."""
+    say(f"[parity] three-call {name}")
+    b = make(name, n)
+    cut = cuts(cutname)
+    c, t = oracle_run(b, cut)
+    v = velo_mod.Velo(b.plane_z, cut)
+    v.reserve(b.n_events, b.n_pix, b.n_pix)
+    off, ids = velo_mod.to_device(b)
+    bufs = v.pipeline_buffers(b.n_events, b.n_pix)
+    v.three_call(off, ids, bufs)
+    torch.cuda.synchronize()
+    assert v.read_status(bufs["status_clu"])[0] == 0
+    assert v.read_status(bufs["status"])[0] == 0
+    assert_clusters_equal(dict(bufs, clu_npix=None), c, b.n_pix)
+    assert_tracks_equal(bufs, t, check_flags=True)
+    T = len(t["trk_planes"])
+    assert_fit_close(np_(bufs["par"], T), t, c, b.plane_z, cut["sigma"])
+
+
 def test_emit_rejected_candidates_and_flags(velo_mod):
     b = make("nominal", 60)
     cut = cuts("ms")
@@ -111,7 +133,7 @@ def test_emit_rejected_candidates_and_flags(velo_mod):
     assert np.any((t["trk_flags"] & 8) == 0)  # some candidates rejected
 
 
-@pytest.mark.parametrize("threads", [64, 128, 256])
+@pytest.mark.parametrize("threads", [64, 128, 256, 512])
 @pytest.mark.parametrize("tile", [0, 1, 2])
 def test_every_launch_configuration_gives_identical_tracks(velo_mod, threads, tile):
     say(f"[parity] launch threads={threads} tile={tile}")

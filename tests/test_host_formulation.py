@@ -134,3 +134,32 @@ def test_seed_windows_contain_every_passing_triplet():
             kd = kd - 65536 if kd > 32767 else (kd + 65536 if kd < -32768 else kd)
             m1 = disc_keys(R_mid, rj)
             assert in_span(int(k1[j]), int(k0[j]) + min(kd, 0), int(k0[j]) + max(kd, 0), m1), j
+
+
+
+def grid_cell1(v):
+    """Cell of a coordinate as the kernels compute it (FP32): 0.5 mm cells over [-40, 40] mm."""
+    c = np.floor((np.asarray(v, f32) + f32(40.0)) * f32(2.0))
+    return np.clip(c, 0, 159).astype(np.int64)
+
+
+def test_grid_disc_search_contains_every_hit_in_the_disc():
+    """The crowded-plane searches visit the cells meeting the square around the
+    disc (centre +- (R + 1e-3)); every hit within R of the centre must lie in one."""
+    rng = np.random.default_rng(3)
+    n = 200000
+    cx = rng.uniform(-41, 41, n).astype(f32)
+    cy = rng.uniform(-41, 41, n).astype(f32)
+    R = rng.choice([0.3, 0.5, 0.66], n).astype(f32)
+    ang = rng.uniform(0, 2 * math.pi, n)
+    rr = R * np.sqrt(rng.uniform(0, 1, n))
+    rr = np.where(rng.random(n) < 0.2, R, rr)  # many exactly on the rim
+    hx = (cx + rr * np.cos(ang)).astype(f32)
+    hy = (cy + rr * np.sin(ang)).astype(f32)
+    dx, dy = hx - cx, hy - cy
+    inside = dx * dx + dy * dy <= R * R
+    rm = R + f32(1e-3)
+    ix, iy = grid_cell1(hx), grid_cell1(hy)
+    ok = (grid_cell1(cx - rm) <= ix) & (ix <= grid_cell1(cx + rm)) & (grid_cell1(cy - rm) <= iy) & (iy <= grid_cell1(cy + rm))
+    assert inside.sum() > 100000
+    assert np.all(ok[inside])
