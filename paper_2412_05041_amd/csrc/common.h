@@ -16,6 +16,8 @@ constexpr int kCells = kGridN * kGridN;
 constexpr float kGridInv = 2.0f;
 constexpr float kGridOrg = 40.0f;
 constexpr int64_t kCellWords = (int64_t)26 * (kCells + 1) + kCells;  // per workgroup
+constexpr int kMaxLdsBlocksPerCu = 8;  // bound of the LDS-tile finder's grid
+constexpr int kLutSmall = 256;         // key buckets of an LDS-tile plane
 constexpr int kWave = 64;
 constexpr int kKeyBits = 16;          // azimuth key resolution
 constexpr int kBuckets = 1024;        // counting-sort buckets of large segments (top 10 key bits)

@@ -45,8 +45,9 @@ constexpr float kPi = 3.14159265358979f;
 constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kRing = 5;  // planes k .. k+4 in the window
-constexpr int kLutSmall = 256;   // key buckets of an LDS-tile plane
 constexpr int kLutLarge = 4096;  // key buckets of a large-event plane
+constexpr int kLutCoarseBits = 6;
+constexpr int kLutCoarse = 1 << kLutCoarseBits;  // key buckets of the per-event coarse index
 constexpr float kKeysPerRad = 10430.378350470453f;  // 2^16 / (2 pi)
 
 #ifdef VELO_PHASE_TIMING
@@ -61,9 +62,16 @@ __device__ unsigned long long g_phase[8];
             ph_t = now;                                                 \
         }                                                               \
     } while (0)
+#define PCOUNT(i, v)                                                    \
+    do {                                                                \
+        if (threadIdx.x == 0) atomicAdd(&g_phase[i], (unsigned long long)(v)); \
+    } while (0)
+#define PCLOCK() wall_clock64()
 #else
 #define PHASE_T0() (void)0
 #define PHASE(i) (void)0
+#define PCOUNT(i, v) (void)0
+#define PCLOCK() 0ull
 #endif
 
 // ---------------------------------------------------------------- storage
@@ -79,7 +87,7 @@ struct Tile {
     int32_t claim[kP];
     uint16_t wid[kRing][kP];  // plane-local cluster index
     uint16_t wk[kRing][kP];
-    uint8_t wu[kRing][kP];
+    uint32_t ubits[kPlanes][(kP + 31) / 32];  // used flags of every plane of the event
     // tracks: upstream end (T1); the downstream end (T3) of a step's new tracks
     // lives in the seeding-slot memory once the seeds are claimed
     float ttx[kT], tty[kT], txb[kT], tyb[kT];
@@ -90,6 +98,7 @@ struct Tile {
     uint16_t cp[kC][3];
     uint8_t calive[kC];
     uint16_t lut[kRing][kLutSmall + 1];  // first position of each key bucket
+    uint16_t clut[kPlanes][kLutCoarse + 1];  // coarse bucket index of every plane of the event
 };
 
 struct Scalars {
@@ -97,6 +106,7 @@ struct Scalars {
     int wsum[16];            // per-wave partial sums of block scans
     float z[kPlanes];        // plane positions (lane-indexed reads stay in LDS)
     int wn[kRing];
+    int wplane[kRing];       // plane held by each ring slot
     int64_t wg[kRing];       // staged (= cluster) base of the plane in each ring slot
     int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
 };
@@ -115,7 +125,11 @@ struct LdsStore {
     __device__ int K(int sl, int i) const { return t->wk[sl][i]; }
     __device__ int L(int sl, int i) const { return t->wid[sl][i]; }  // plane-local index
     __device__ int64_t ID(int sl, int i) const { return s->wg[sl] + t->wid[sl][i]; }
-    __device__ uint8_t& U(int sl, int i) { return t->wu[sl][i]; }
+    __device__ bool UP(int j, int i) const { return (t->ubits[j][i >> 5] >> (i & 31)) & 1u; }
+    __device__ void set_UP(int j, int i) { atomicOr(&t->ubits[j][i >> 5], 1u << (i & 31)); }
+    // used flag of position i of plane j, held in ring slot sl
+    __device__ bool U(int, int j, int i) const { return UP(j, i); }
+    __device__ void set_U(int, int j, int i) { set_UP(j, i); }
     __device__ int32_t* claim(int) { return t->claim; }
     __device__ int32_t* claimT(int64_t) { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
     __device__ uint64_t* slotA(int role) { return t->slota[role]; }
@@ -166,7 +180,8 @@ struct GlobalStore {
     __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
     __device__ int L(int sl, int i) const { return (int)(w->sid[s->wg[sl] + i] - s->wg[sl]); }
     __device__ int64_t ID(int sl, int i) const { return w->sid[s->wg[sl] + i]; }
-    __device__ uint8_t& U(int sl, int i) { return w->used[s->wg[sl] + i]; }
+    __device__ bool U(int sl, int, int i) const { return w->used[s->wg[sl] + i] != 0; }
+    __device__ void set_U(int sl, int, int i) { w->used[s->wg[sl] + i] = 1; }
     __device__ int32_t* claim(int sl) { return w->g_claim + s->wg[sl]; }
     __device__ int32_t* claimT(int64_t g) { return w->g_claim + g; }
     __device__ uint64_t* slotA(int role) { return w->g_slota + s->cb[seed_k + role]; }
@@ -409,31 +424,30 @@ __device__ __forceinline__ void lut_entries(uint16_t* lut, int i, int n, int key
         for (int b = bi + 1; b <= kN; ++b) lut[b] = (uint16_t)n;
 }
 
-// Plane k into ring slot k % kRing (LDS tile): the used flags of the plane
-// leaving the slot go back to global memory, then hits, flags and bucket
-// index are written by the thread owning each position (one barrier).
+// Plane k into ring slot k % kRing (LDS tile): hits, used flags and bucket
+// index are written by the thread owning each position (one barrier).  A
+// coarse bucket index of the plane is kept for the whole event: it serves the
+// downstream completion once the plane has left the ring, as do the used flags
+// of every plane, which stay in LDS.
 template <int kT, int kPF, class S>
 __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& pf) {
     Scalars& sc = *st.s;
     const int sl = k % kRing;
     auto* t = st.t;
-    if (k + kRing < kPlanes) {
-        const int64_t og = sc.cb[k + kRing];
-        const int on = (int)(sc.cb[k + kRing + 1] - og);
-        for (int i = threadIdx.x; i < on; i += kT) a.w.used[og + i] = t->wu[sl][i];
-    }
     const int64_t g = sc.cb[k];
     const int n = (int)(sc.cb[k + 1] - g);
     constexpr int kShift = S::kLutShift, kN = S::kLutN;
     uint16_t* lut = t->lut[sl];
+    uint16_t* clut = t->clut[k];
+    for (int wd = threadIdx.x; wd < (n + 31) / 32; wd += kT) t->ubits[k][wd] = 0u;
     auto put = [&](int i, float x, float y, int key, int kprev, int id) {
         t->wx[sl][i] = x;
         t->wy[sl][i] = y;
         t->wk[sl][i] = (uint16_t)key;
         t->wid[sl][i] = (uint16_t)id;
-        t->wu[sl][i] = 0;
         t->claim[i] = kIntMax;
         lut_entries<kShift, kN>(lut, i, n, key, kprev);
+        lut_entries<16 - kLutCoarseBits, kLutCoarse>(clut, i, n, key, kprev);
     };
 #pragma unroll
     for (int r = 0; r < kPF; ++r) {
@@ -444,9 +458,12 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
         put(i, a.w.sx[g + i], a.w.sy[g + i], a.w.skey[g + i], (int)a.w.skey[g + i - 1], (int)(a.w.sid[g + i] - g));
     if (n == 0)
         for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
+    if (n == 0)
+        for (int b = threadIdx.x; b <= kLutCoarse; b += kT) clut[b] = 0;
     if (threadIdx.x == 0) {
         sc.wg[sl] = g;
         sc.wn[sl] = n;
+        sc.wplane[sl] = k;
     }
     __syncthreads();
 }
@@ -466,6 +483,7 @@ __device__ void load_plane_global(S& st, int k) {
     if (threadIdx.x == 0) {
         sc.wg[sl] = g;
         sc.wn[sl] = n;
+        sc.wplane[sl] = k;
     }
     int32_t* cs = st.cell + (int64_t)k * (kCells + 1);
     int32_t* fill = st.cell + (int64_t)kPlanes * (kCells + 1);
@@ -519,7 +537,7 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
                 const uint16_t* lut = st.lut(sl);
                 auto key = [&](int i) { return st.K(sl, i); };
                 want = best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, n, v); }, key,
-                                [&](int i) { return st.U(sl, i); },
+                                [&](int i) { return st.U(sl, k, i); },
                                 [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
                                 [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
             }
@@ -531,7 +549,7 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
     for (int t = threadIdx.x; t < nt; t += kT) {
         const int i = st.twant(t);
         if (i >= 0 && claim[i] == t) {
-            st.U(sl, i) = 1;
+            st.set_U(sl, k, i);
             const float xh = st.X(sl, i), yh = st.Y(sl, i);
             const int kb = st.tkb(t);
             const float dz = sc.z[kb] - sc.z[k];
@@ -584,7 +602,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     // asin(R_mid/r0) of that arc.
     for (int i0 = threadIdx.x; i0 < n0; i0 += kT) {
         int cnt = 0, ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0, m1 = 0;
-        if (!st.U(s0, i0)) {
+        if (!st.U(s0, k, i0)) {
             const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
             const int k0 = st.K(s0, i0);
             const float r0 = sqrtf(x0 * x0 + y0 * y0);
@@ -629,7 +647,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
         const int o = pi - pref[i0];
         const int len0 = eb[n0 + i0] - eb[i0];
         const int i2 = o < len0 ? eb[i0] + o : eb[2 * n0 + i0] + (o - len0);
-        if (st.U(s2, i2)) continue;
+        if (st.U(s2, k + 2, i2)) continue;
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
         const float tx = (st.X(s2, i2) - x0) / dz2;
         const float ty = (st.Y(s2, i2) - y0) / dz2;
@@ -640,7 +658,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
         const float ex = x0 + tx * dz1;
         const float ey = y0 + ty * dz1;
         auto try_mid = [&](int i1, float x1, float y1) {
-            if (st.U(s1, i1)) return;
+            if (st.U(s1, k + 1, i1)) return;
             const float dx = x1 - ex;
             const float dy = y1 - ey;
             const float q = dx * dx + dy * dy;
@@ -729,9 +747,9 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
             const uint32_t kB = keyB(c);
             if (A0[i0] == kA && A1[i1] == kA && A2[i2] == kA && B0[i0] == kB && B1[i1] == kB && B2[i2] == kB) {
                 st.calive(c) = 2;
-                st.U(s0, i0) = 1;
-                st.U(s1, i1) = 1;
-                st.U(s2, i2) = 1;
+                st.set_U(s0, k, i0);
+                st.set_U(s1, k + 1, i1);
+                st.set_U(s2, k + 2, i2);
             }
         }
         __syncthreads();
@@ -744,7 +762,7 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
             B0[i0] = ~0u; B1[i1] = ~0u; B2[i2] = ~0u;
             if (al == 2) {
                 st.calive(c) = 3;
-            } else if (st.U(s0, i0) || st.U(s1, i1) || st.U(s2, i2)) {
+            } else if (st.U(s0, k, i0) || st.U(s1, k + 1, i1) || st.U(s2, k + 2, i2)) {
                 st.calive(c) = 0;
             } else {
                 any = 1;
@@ -757,9 +775,9 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
 // One downstream completion step (plane j) of the tracks [t0, t1).  The plane
 // is read through the accessors given (LDS ring or global staging).  Returns
 // (uniformly) whether any track was still open.
-template <int kT, class S, class LF, class KF, class UF, class XF, class YF, class IF>
+template <int kT, class S, class LF, class KF, class UF, class SF, class XF, class YF, class IF>
 __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, LF lower,
-                               KF key, UF used, XF xf, YF yf, IF idf, int64_t gbase) {
+                               KF key, UF used, SF set_used, XF xf, YF yf, IF idf, int64_t gbase) {
     const Params& p = a.p;
     if constexpr (!S::kLarge) {
         for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
@@ -786,7 +804,7 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
     for (int t = t0 + threadIdx.x; t < t1; t += kT) {
         const int i = st.twant(t);
         if (i >= 0 && claimT[i] == t) {
-            used(i) = 1;
+            set_used(i);
             const float xh = xf(i), yh = yf(i);
             const int kb = st.dkb(t);
             const float dz = st.s->z[kb] - st.s->z[j];
@@ -888,19 +906,35 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             auto key = [&](int i) { return st.K(sl, i); };
             open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0),
                                       [&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
-                                      [&](int i) -> uint8_t& { return st.U(sl, i); },
+                                      [&](int i) { return st.U(sl, j, i); }, [&](int i) { st.set_U(sl, j, i); },
                                       [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
                                       [&](int i) { return st.L(sl, i); }, sc.wg[sl]);
+            PCOUNT(5, 1);
         } else {
+            const uint64_t tg = PCLOCK();
             const int64_t g = sc.cb[j];
             const Work& w = a.w;
             const int nj = (int)(sc.cb[j + 1] - g);
             auto key = [&](int i) { return (int)w.skey[g + i]; };
-            open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
-                                      [&](int v) { return lower_key(key, nj, v); }, key,
-                                      [&](int i) -> uint8_t& { return w.used[g + i]; },
-                                      [&](int i) { return w.sx[g + i]; }, [&](int i) { return w.sy[g + i]; },
-                                      [&](int i) { return (int)(w.sid[g + i] - g); }, g);
+            auto xf = [&](int i) { return w.sx[g + i]; };
+            auto yf = [&](int i) { return w.sy[g + i]; };
+            auto idf = [&](int i) { return (int)(w.sid[g + i] - g); };
+            if constexpr (S::kLarge) {
+                open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
+                                          [&](int v) { return lower_key(key, nj, v); }, key,
+                                          [&](int i) { return w.used[g + i] != 0; }, [&](int i) { w.used[g + i] = 1; },
+                                          xf, yf, idf, g);
+            } else {
+                // a plane that has left the ring: hits from global staging through
+                // its coarse bucket index, used flags in LDS
+                const uint16_t* clut = st.t->clut[j];
+                open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
+                                          [&](int v) { return lower_lut<16 - kLutCoarseBits>(clut, key, nj, v); }, key,
+                                          [&](int i) { return st.UP(j, i); }, [&](int i) { st.set_UP(j, i); },
+                                          xf, yf, idf, g);
+            }
+            PCOUNT(6, 1);
+            PCOUNT(7, PCLOCK() - tg);
         }
         if (!open) break;
     }

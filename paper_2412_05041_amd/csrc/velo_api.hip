@@ -175,7 +175,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
 
 int grid_for(velo_ctx* c, int n_events) {
     const int per_cu = find_blocks_per_cu(c->threads, c->tile);
-    const int g = std::max(1, c->n_cu * std::max(per_cu, 1));
+    const int g = std::max(1, c->n_cu * std::min(std::max(per_cu, 1), kMaxLdsBlocksPerCu));
     return std::max(1, std::min(n_events, g));
 }
 
