@@ -693,26 +693,51 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     return sc.n_cand <= cap;
 }
 
+// Synchronisation of a group of kG threads of a kT-thread workgroup: the whole
+// workgroup (barrier) or its first wave alone (lockstep lanes: an LDS fence
+// orders the accesses, no barrier needed).
+template <int kG, int kT>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (kG == kT) {
+        __syncthreads();
+    } else {
+        static_assert(kG == kWave, "a sub-group is one wave");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int kG, int kT>
+__device__ __forceinline__ bool group_or(int v) {
+    if constexpr (kG == kT) {
+        return __syncthreads_or(v) != 0;
+    } else {
+        group_sync<kG, kT>();
+        return __ballot(v) != 0ull;
+    }
+}
+
 // T2 greedy claiming by rounds of local minima; winners end marked 3.
-// Candidate states: 1 alive, 2 won this round, 3 settled winner, 0 dead.
-template <int kT, class S>
-__device__ void claim_seeds(S& st, const FindArgs& a, int k) {
-    Scalars& sc = *st.s;
+// Candidate states: 1 alive, 2 won this round, 3 settled winner, 0 dead.  Run
+// by a group of kG threads (the workgroup, or its first wave when the
+// candidates fit it).  Only the slots of hits that some candidate uses are
+// read, so only those are cleared.
+template <int kG, int kT, class S>
+__device__ void claim_rounds(S& st, int k, int nc) {
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
-    const int nc = sc.n_cand;
     uint64_t* A0 = st.slotA(0);
     uint64_t* A1 = st.slotA(1);
     uint64_t* A2 = st.slotA(2);
     uint32_t* B0 = st.slotB(0);
     uint32_t* B1 = st.slotB(1);
     uint32_t* B2 = st.slotB(2);
-    const int nr[3] = {sc.wn[s0], sc.wn[s1], sc.wn[s2]};
-    for (int r = 0; r < 3; ++r) {
-        uint64_t* A = st.slotA(r);
-        uint32_t* B = st.slotB(r);
-        for (int i = threadIdx.x; i < nr[r]; i += kT) { A[i] = ~0ull; B[i] = ~0u; }
+    for (int c = threadIdx.x; c < nc; c += kG) {
+        const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
+        A0[i0] = ~0ull; A1[i1] = ~0ull; A2[i2] = ~0ull;
+        B0[i0] = ~0u; B1[i1] = ~0u; B2[i2] = ~0u;
     }
-    __syncthreads();
+    group_sync<kG, kT>();
     auto keyA = [&](int c) {
         return ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
     };
@@ -720,17 +745,17 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
         return ((uint32_t)st.L(s1, st.cp(c, 1)) << 16) | (uint32_t)st.L(s2, st.cp(c, 2));
     };
     while (true) {
-        for (int c = threadIdx.x; c < nc; c += kT) {
+        for (int c = threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const uint64_t kA = keyA(c);
             atomicMin((unsigned long long*)(A0 + st.cp(c, 0)), kA);
             atomicMin((unsigned long long*)(A1 + st.cp(c, 1)), kA);
             atomicMin((unsigned long long*)(A2 + st.cp(c, 2)), kA);
         }
-        __syncthreads();
+        group_sync<kG, kT>();
         // per hit: among the candidates holding the smallest (q, h0) there,
         // the smallest (h1, h2) -- the per-hit minimum of the full key
-        for (int c = threadIdx.x; c < nc; c += kT) {
+        for (int c = threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             const uint64_t kA = keyA(c);
@@ -739,8 +764,8 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
             if (A1[i1] == kA) atomicMin(B1 + i1, kB);
             if (A2[i2] == kA) atomicMin(B2 + i2, kB);
         }
-        __syncthreads();
-        for (int c = threadIdx.x; c < nc; c += kT) {
+        group_sync<kG, kT>();
+        for (int c = threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             const uint64_t kA = keyA(c);
@@ -752,9 +777,9 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
                 st.set_U(s2, k + 2, i2);
             }
         }
-        __syncthreads();
+        group_sync<kG, kT>();
         int any = 0;
-        for (int c = threadIdx.x; c < nc; c += kT) {
+        for (int c = threadIdx.x; c < nc; c += kG) {
             const uint8_t al = st.calive(c);
             if (al != 1 && al != 2) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
@@ -768,23 +793,35 @@ __device__ void claim_seeds(S& st, const FindArgs& a, int k) {
                 any = 1;
             }
         }
-        if (!__syncthreads_or(any)) break;
+        if (!group_or<kG, kT>(any)) break;
     }
 }
 
-// One downstream completion step (plane j) of the tracks [t0, t1).  The plane
-// is read through the accessors given (LDS ring or global staging).  Returns
-// (uniformly) whether any track was still open.
-template <int kT, class S, class LF, class KF, class UF, class SF, class XF, class YF, class IF>
+template <int kT, class S>
+__device__ void claim_seeds(S& st, const FindArgs&, int k) {
+    const int nc = st.s->n_cand;
+    if (kT > kWave && nc <= kWave) {
+        if (threadIdx.x < kWave) claim_rounds<kWave, kT>(st, k, nc);
+        __syncthreads();
+    } else {
+        claim_rounds<kT, kT>(st, k, nc);
+    }
+}
+
+// One downstream completion step (plane j) of the tracks [t0, t1), by a group
+// of kG threads (the workgroup, or its first wave when the tracks fit it).  The
+// plane is read through the accessors given (LDS ring or global staging).
+// Returns (uniformly over the group) whether any track was still open.
+template <int kG, int kT, class S, class LF, class KF, class UF, class SF, class XF, class YF, class IF>
 __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, LF lower,
                                KF key, UF used, SF set_used, XF xf, YF yf, IF idf, int64_t gbase) {
     const Params& p = a.p;
     if constexpr (!S::kLarge) {
-        for (int i = threadIdx.x; i < n; i += kT) claimT[i] = kIntMax;
-        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kG) claimT[i] = kIntMax;
+        group_sync<kG, kT>();
     }
     int active = 0;
-    for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+    for (int t = t0 + threadIdx.x; t < t1; t += kG) {
         int want = -1;
         const int kb = st.dkb(t);
         if (j - kb - 1 <= p.max_skip) {
@@ -800,8 +837,8 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
         }
         st.twant(t) = want;
     }
-    if (!__syncthreads_or(active)) return false;
-    for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+    if (!group_or<kG, kT>(active)) return false;
+    for (int t = t0 + threadIdx.x; t < t1; t += kG) {
         const int i = st.twant(t);
         if (i >= 0 && claimT[i] == t) {
             set_used(i);
@@ -817,13 +854,13 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
             a.w.chits[(st.slot0 + t) * kPlanes + j] = (int32_t)(gbase + idf(i));
         }
     }
-    __syncthreads();
+    group_sync<kG, kT>();
     if constexpr (S::kLarge) {
-        for (int t = t0 + threadIdx.x; t < t1; t += kT) {
+        for (int t = t0 + threadIdx.x; t < t1; t += kG) {
             const int i = st.twant(t);
             if (i >= 0) claimT[i] = kIntMax;
         }
-        __syncthreads();
+        group_sync<kG, kT>();
     }
     return true;
 }
@@ -896,7 +933,10 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     if (threadIdx.x == 0) sc.n_tracks = t0 + nw;
     __syncthreads();
 
-    // T3: downstream completion of tracks [t0, t0 + nw), planes k+3 .. 25
+    // T3: downstream completion of tracks [t0, t0 + nw), planes k+3 .. 25; by
+    // the first wave alone when the new tracks fit it (no workgroup barriers)
+    auto t3 = [&](auto grp) {
+    constexpr int kG = decltype(grp)::value;
     for (int j = k + 3; j < kPlanes; ++j) {
         bool open;
         if (!S::kLarge && j < k + kRing) {
@@ -904,7 +944,7 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             const int nj = sc.wn[sl];
             const uint16_t* lut = st.lut(sl);
             auto key = [&](int i) { return st.K(sl, i); };
-            open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0),
+            open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0),
                                       [&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
                                       [&](int i) { return st.U(sl, j, i); }, [&](int i) { st.set_U(sl, j, i); },
                                       [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
@@ -920,7 +960,7 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             auto yf = [&](int i) { return w.sy[g + i]; };
             auto idf = [&](int i) { return (int)(w.sid[g + i] - g); };
             if constexpr (S::kLarge) {
-                open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
+                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
                                           [&](int v) { return lower_key(key, nj, v); }, key,
                                           [&](int i) { return w.used[g + i] != 0; }, [&](int i) { w.used[g + i] = 1; },
                                           xf, yf, idf, g);
@@ -928,7 +968,7 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
                 // a plane that has left the ring: hits from global staging through
                 // its coarse bucket index, used flags in LDS
                 const uint16_t* clut = st.t->clut[j];
-                open = complete_plane<kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
+                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
                                           [&](int v) { return lower_lut<16 - kLutCoarseBits>(clut, key, nj, v); }, key,
                                           [&](int i) { return st.UP(j, i); }, [&](int i) { st.set_UP(j, i); },
                                           xf, yf, idf, g);
@@ -937,6 +977,13 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             PCOUNT(7, PCLOCK() - tg);
         }
         if (!open) break;
+    }
+    };
+    if (kT > kWave && nw <= kWave) {
+        if (threadIdx.x < kWave) t3(std::integral_constant<int, kWave>{});
+        __syncthreads();
+    } else {
+        t3(std::integral_constant<int, kT>{});
     }
     return true;
 }
