@@ -126,13 +126,14 @@ __device__ void stage_segment(const float* cx, const float* cy, int m, int64_t g
     }
 }
 
-// Clustering of one segment with segment-local numbering.  kSmall: parent and
-// rank arrays and the sums in LDS; otherwise in the per-pixel global scratch.
-// Writes pix_clu = local rank, seg_m = cluster count and, at pixel-indexed
-// scratch positions p0 + j, the centroid x, y and pixel count of cluster j.
-template <bool kSmall, typename Id, typename P, typename R>
-__device__ void cluster_local(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
-                              unsigned long long* s_sum, int refuse) {
+// Clustering of one segment with segment-local numbering, for segments above
+// kCap pixels: parent and rank arrays and the sums in the per-pixel global
+// scratch.  Writes pix_clu = local rank, seg_m = cluster count and, at
+// pixel-indexed scratch positions p0 + j, the centroid x, y and pixel count of
+// cluster j.  refuse: the scratch cannot hold the segment (overflow flag).
+template <typename Id, typename P, typename R>
+__device__ void cluster_global(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
+                               int refuse) {
     const int lane = threadIdx.x;
     const Work& w = a.w;
     const int e = seg / kPlanes;
@@ -170,39 +171,19 @@ __device__ void cluster_local(const ClusterArgs& a, int seg, int p0, int n, cons
     }
     __syncthreads();
     for (int i = lane; i < n; i += kWave) rnk[i] = par[rnk[i]];
-    if (kSmall) {
-        for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
-    } else {
-        for (int j = lane; j < m; j += kWave) { w.g_sc[p0 + j] = 0; w.g_sr[p0 + j] = 0; w.g_cnt[p0 + j] = 0; }
-    }
+    for (int j = lane; j < m; j += kWave) { w.g_sc[p0 + j] = 0; w.g_sr[p0 + j] = 0; w.g_cnt[p0 + j] = 0; }
     __syncthreads();
     for (int i = lane; i < n; i += kWave) {
         const int rk = rnk[i];
         a.pix_clu[p0 + i] = rk;
         const uint32_t id = ids[i];
-        const uint32_t c = id % kSide, r = id / kSide;
-        if (kSmall) {
-            // packed [sum_c:32 | count:11 | sum_r:21]; n <= 512 keeps the fields apart
-            atomicAdd(s_sum + rk, ((unsigned long long)c << 32) | (1ull << 21) | (unsigned long long)r);
-        } else {
-            atomicAdd(w.g_sc + p0 + rk, c);
-            atomicAdd(w.g_sr + p0 + rk, r);
-            atomicAdd(w.g_cnt + p0 + rk, 1u);
-        }
+        atomicAdd(w.g_sc + p0 + rk, id % kSide);
+        atomicAdd(w.g_sr + p0 + rk, id / kSide);
+        atomicAdd(w.g_cnt + p0 + rk, 1u);
     }
     __syncthreads();
     for (int j = lane; j < m; j += kWave) {
-        uint32_t sc, sr, cnt;
-        if (kSmall) {
-            const unsigned long long v = s_sum[j];
-            sc = (uint32_t)(v >> 32);
-            cnt = (uint32_t)((v >> 21) & 0x7ffu);
-            sr = (uint32_t)(v & 0x1fffffu);
-        } else {
-            sc = w.g_sc[p0 + j];
-            sr = w.g_sr[p0 + j];
-            cnt = w.g_cnt[p0 + j];
-        }
+        const uint32_t sc = w.g_sc[p0 + j], sr = w.g_sr[p0 + j], cnt = w.g_cnt[p0 + j];
         const float fn = (float)cnt;
         // centroid parked in the scratch (same slots as the sums: read before write)
         w.g_sc[p0 + j] = __float_as_uint(((float)sc / fn - 726.5f) * 0.055f);
@@ -212,11 +193,103 @@ __device__ void cluster_local(const ClusterArgs& a, int seg, int p0, int n, cons
     if (lane == 0) w.seg_m[seg] = m;
 }
 
+// Clustering of a segment of at most kCap pixels, one wave.  Per-pixel state
+// (id, root, rank; pixel i = lane + 64 r) stays in registers; only the ids and
+// the union-find parents live in LDS (kCap words each), and once the ranks are
+// known that space holds the packed per-cluster sums.  Same outputs as
+// cluster_global.
+__device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsigned long long* s_buf) {
+    constexpr int R = kCap / kWave;
+    uint32_t* s_id = reinterpret_cast<uint32_t*>(s_buf);
+    int32_t* s_par = reinterpret_cast<int32_t*>(s_id + kCap);
+    const int lane = threadIdx.x;
+    const Work& w = a.w;
+    uint32_t id[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        id[r] = i < n ? a.pix_id[p0 + i] : 0u;
+        if (i < n) {
+            s_id[i] = id[r];
+            s_par[i] = i;
+        }
+    }
+    __syncthreads();
+    int bad = 0;
+    if (a.validate) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + r * kWave;
+            if (i < n && (id[r] >= (uint32_t)(kSide * kSide) || (i > 0 && s_id[i - 1] >= id[r]))) bad = 1;
+        }
+    }
+    if (__syncthreads_or(bad)) {
+        for (int i = lane; i < n; i += kWave) a.pix_clu[p0 + i] = -1;
+        if (lane == 0) {
+            w.seg_m[seg] = 0;
+            set_event_flag(a.status, seg / kPlanes, EV_BAD_INPUT, 2);
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        if (i < n) unite_neighbours(s_id, s_par, i);
+    }
+    __syncthreads();
+    int root[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        root[r] = i < n ? find_root(s_par, i) : -1;
+    }
+    __syncthreads();
+    // number the roots in index order; par[root] := its rank
+    int m = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        const int isroot = root[r] == i ? 1 : 0;
+        int tot;
+        const int ex = wave_excl_scan(isroot, &tot);
+        if (isroot) s_par[i] = m + ex;
+        m += tot;
+    }
+    __syncthreads();
+    int rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rank[r] = root[r] >= 0 ? s_par[root[r]] : 0;
+    __syncthreads();
+    // ids and parents are dead: the same words hold the packed sums
+    // [sum_c:32 | count:11 | sum_r:21]; n <= 512 keeps the fields apart
+    unsigned long long* s_sum = s_buf;
+    for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        if (i < n) {
+            a.pix_clu[p0 + i] = rank[r];
+            const uint32_t c = id[r] % kSide, rr = id[r] / kSide;
+            atomicAdd(s_sum + rank[r], ((unsigned long long)c << 32) | (1ull << 21) | (unsigned long long)rr);
+        }
+    }
+    __syncthreads();
+    for (int j = lane; j < m; j += kWave) {
+        const unsigned long long v = s_sum[j];
+        const uint32_t sc = (uint32_t)(v >> 32);
+        const uint32_t cnt = (uint32_t)((v >> 21) & 0x7ffu);
+        const uint32_t sr = (uint32_t)(v & 0x1fffffu);
+        const float fn = (float)cnt;
+        w.g_sc[p0 + j] = __float_as_uint(((float)sc / fn - 726.5f) * 0.055f);
+        w.g_sr[p0 + j] = __float_as_uint(((float)sr / fn - 726.5f) * 0.055f);
+        w.g_cnt[p0 + j] = cnt;
+    }
+    if (lane == 0) w.seg_m[seg] = m;
+}
+
 __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
-    __shared__ uint32_t s_id[kCap];
-    __shared__ int32_t s_par[kCap];
-    __shared__ int32_t s_rnk[kCap];
-    __shared__ unsigned long long s_sum[kCap];
+    __shared__ unsigned long long s_buf[kCap];
     const int seg = blockIdx.x;
     if (seg >= a.n_seg) return;
     const Work& w = a.w;
@@ -225,26 +298,33 @@ __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
     // the per-pixel scratch covers pixel positions below its capacity
     const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
     if (n <= kCap && !refuse) {
-        for (int i = threadIdx.x; i < n; i += kWave) s_id[i] = a.pix_id[p0 + i];
-        __syncthreads();
-        cluster_local<true>(a, seg, p0, n, s_id, s_par, s_rnk, s_sum, 0);
+        cluster_small(a, seg, p0, n, s_buf);
     } else {
-        cluster_local<false>(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, s_sum, refuse);
+        cluster_global(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, refuse);
     }
 }
 
 // Exclusive scan of the segment cluster counts -> clu_off (single workgroup).
+// Each thread scans a contiguous chunk, reading it 8 counts at a time so that
+// the loads of a group are in flight together.
 __global__ __launch_bounds__(1024) void k_scan_seg(ClusterArgs a) {
     __shared__ int64_t s_w[1024 / kWave];
     __shared__ int64_t s_carry;
     const Work& w = a.w;
     const int n = a.n_seg;
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    // each thread scans a contiguous chunk
     const int per = (n + 1023) / 1024;
-    const int b0 = threadIdx.x * per;
+    const int b0 = min(n, (int)threadIdx.x * per), b1 = min(n, b0 + per);
     int64_t loc = 0;
-    for (int i = b0; i < b0 + per && i < n; ++i) loc += w.seg_m[i];
+    int i = b0;
+    for (; i + 8 <= b1; i += 8) {
+        int v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = w.seg_m[i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) loc += v[q];
+    }
+    for (; i < b1; ++i) loc += w.seg_m[i];
     int tot;
     // 64-bit chunk sums are small (< 2^31 clusters in a batch): scan them as int
     const int ex = wave_excl_scan((int)loc, &tot);
@@ -252,12 +332,23 @@ __global__ __launch_bounds__(1024) void k_scan_seg(ClusterArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t c = 0;
-        for (int i = 0; i < 1024 / kWave; ++i) { const int64_t t = s_w[i]; s_w[i] = c; c += t; }
+        for (int q = 0; q < 1024 / kWave; ++q) { const int64_t t = s_w[q]; s_w[q] = c; c += t; }
         s_carry = c;
     }
     __syncthreads();
     int64_t run = s_w[wid] + ex;
-    for (int i = b0; i < b0 + per && i < n; ++i) {
+    i = b0;
+    for (; i + 8 <= b1; i += 8) {
+        int v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = w.seg_m[i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a.clu_off[i + q] = (int32_t)run;
+            run += v[q];
+        }
+    }
+    for (; i < b1; ++i) {
         a.clu_off[i] = (int32_t)run;
         run += w.seg_m[i];
     }
