@@ -64,6 +64,7 @@ struct Work {
     uint8_t* cflags;      // TRK_* flags
     float* clogit;
     uint16_t* cfeat;      // [slot][16] BF16 standardised features
+    float* cpar;          // [slot][8] the acceptance fit (x, y, z_ref, tx, ty, chi2, ndof, 0)
     // per event
     int32_t* ev_ncand;    // candidates
     int32_t* ev_nout;     // tracks to output

@@ -1141,6 +1141,9 @@ __global__ __launch_bounds__(256) void k_accept(FindArgs a) {
         const uint32_t mask = a.w.cmask[slot];
         const int32_t* ch = a.w.chits + slot * kPlanes;
         const FitResult f = fit_track_hits([&](int k, int) { return ch[k]; }, mask, a.clu_x, a.clu_y, p.z, p.sigma);
+        float4* fo = reinterpret_cast<float4*>(a.w.cpar + slot * 8);  // reused by the output step
+        fo[0] = make_float4(f.xr, f.yr, f.zr, f.tx);
+        fo[1] = make_float4(f.ty, f.chi2, (float)f.ndof, 0.0f);
         const float lim = f.n == 3 ? p.c3 : p.c4;
         const bool plain = f.chi2 / (float)f.ndof <= lim;
         uint8_t fl = plain ? TRK_PLAIN : 0;

@@ -1,6 +1,7 @@
 // k_output.hip -- bookkeeping kernels: workspace reset, largest-first event
-// order, per-event scans, CSR compaction of the accepted tracks (with the fit
-// fused in the pipeline), and the standalone least-squares fit.
+// order, per-event scans, CSR compaction of the accepted tracks (with their
+// fit parameters, which the acceptance step already computed), and the
+// standalone least-squares fit.
 #include "fitfeat.h"
 #include "kernels.h"
 
@@ -141,7 +142,12 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
                 int j = 0;
                 for (int k = 0; k < kPlanes; ++k)
                     if (mask & (1u << k)) a.trk_hit[h + j++] = ch[k];
-                if (a.par) fit_track(a.trk_hit + h, mask, a.clu_x, a.clu_y, a.p, a.par + t * 8);
+                if (a.par) {  // the acceptance step's fit of these hits (same function, same bits)
+                    const float4* src = reinterpret_cast<const float4*>(w.cpar + (slot0 + c) * 8);
+                    float4* dst = reinterpret_cast<float4*>(a.par + t * 8);
+                    dst[0] = src[0];
+                    dst[1] = src[1];
+                }
             } else {
                 overflow = true;
             }

@@ -121,6 +121,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
     w.cflags = carve<uint8_t>(cur, C);
     w.clogit = carve<float>(cur, C);
     w.cfeat = carve<uint16_t>(cur, C * 16);
+    w.cpar = carve<float>(cur, C * 8);
     w.ev_ncand = carve<int32_t>(cur, E);
     w.ev_nout = carve<int32_t>(cur, E);
     w.ev_nouthit = carve<int32_t>(cur, E);
