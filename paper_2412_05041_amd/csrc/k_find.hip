@@ -158,8 +158,10 @@ struct LdsStore {
         t->cp[i][0] = (uint16_t)a; t->cp[i][1] = (uint16_t)b; t->cp[i][2] = (uint16_t)c;
     }
     __device__ uint8_t& calive(int i) { return t->calive[i]; }
-    __device__ uint64_t* wkey64() { return &t->slota[0][0]; }  // winner keys (after the rounds)
-    __device__ uint32_t* wtmp() { return &t->slotb[0][0]; }
+    // winner keys and winner list (after the rounds), clear of the downstream
+    // state that overlays slota
+    __device__ uint64_t* wkey64() { return reinterpret_cast<uint64_t*>(&t->slotb[0][0]); }
+    __device__ uint32_t* wtmp() { return &t->slotb[2][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
     static constexpr int kLutN = kLutSmall;
@@ -464,6 +466,8 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
         sc.wg[sl] = g;
         sc.wn[sl] = n;
         sc.wplane[sl] = k;
+        sc.n_cand = 0;  // the step's seed and winner counters
+        sc.n_acc = 0;
     }
     __syncthreads();
 }
@@ -484,6 +488,8 @@ __device__ void load_plane_global(S& st, int k) {
         sc.wg[sl] = g;
         sc.wn[sl] = n;
         sc.wplane[sl] = k;
+        sc.n_cand = 0;  // the step's seed and winner counters
+        sc.n_acc = 0;
     }
     int32_t* cs = st.cell + (int64_t)k * (kCells + 1);
     int32_t* fill = st.cell + (int64_t)kPlanes * (kCells + 1);
@@ -563,11 +569,15 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nt; t += kT) {
-        const int i = st.twant(t);
-        if (i >= 0) claim[i] = kIntMax;
+    if constexpr (S::kLarge) {
+        // the global claim words of a plane serve T3 later: leave them clear
+        // (an LDS tile resets its claim words when the next plane is loaded)
+        for (int t = threadIdx.x; t < nt; t += kT) {
+            const int i = st.twant(t);
+            if (i >= 0) claim[i] = kIntMax;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // T2 candidate enumeration, load-balanced over (h0, h2) pairs: (A) every
@@ -581,9 +591,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     const Params& p = a.p;
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const int n0 = sc.wn[s0], n1 = sc.wn[s1], n2 = sc.wn[s2];
-    if (threadIdx.x == 0) sc.n_cand = 0;
-    __syncthreads();
-    if (n0 == 0 || n1 == 0 || n2 == 0) return true;
+    if (n0 == 0 || n1 == 0 || n2 == 0) return true;  // sc.n_cand was cleared with the plane load
     const float dz2 = p.z[k + 2] - p.z[k];
     const float dz1 = p.z[k + 1] - p.z[k];
     const int cap = st.cap_cand();
@@ -600,7 +608,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     // radius grows: h2 lies in that wedge, and the predicted middle point lies
     // between the azimuths of h0 and h2 at radius >= r0, so h1 is within
     // asin(R_mid/r0) of that arc.
-    for (int i0 = threadIdx.x; i0 < n0; i0 += kT) {
+    auto window = [&](int i0) {
         int cnt = 0, ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0, m1 = 0;
         if (!st.U(s0, k, i0)) {
             const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
@@ -618,16 +626,37 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
             }
             cnt = (rb0 - ra0) + (rb1 - ra1);
         }
-        pref[i0] = cnt;
         eb[i0] = ra0;
         eb[n0 + i0] = rb0;
         eb[2 * n0 + i0] = ra1;
         eb[3 * n0 + i0] = rb1;
         eb[4 * n0 + i0] = m1;
+        return cnt;
+    };
+    if (n0 <= kT) {
+        // (A + B) one h0 per thread; the window sizes scanned across the
+        // workgroup in registers (wave scans + per-wave totals)
+        const int cnt = (int)threadIdx.x < n0 ? window(threadIdx.x) : 0;
+        int tot;
+        const int ex = wave_excl_scan(cnt, &tot);
+        const int wv = threadIdx.x / kWave;
+        if ((threadIdx.x % kWave) == 0) sc.wsum[wv] = tot;
+        __syncthreads();
+        int base = 0, total = 0;
+        for (int q = 0; q < kT / kWave; ++q) {
+            const int v = sc.wsum[q];
+            base += q < wv ? v : 0;
+            total += v;
+        }
+        if ((int)threadIdx.x < n0) pref[threadIdx.x] = base + ex;
+        if (threadIdx.x == 0) pref[n0] = total;
+        __syncthreads();
+    } else {
+        for (int i0 = threadIdx.x; i0 < n0; i0 += kT) pref[i0] = window(i0);
+        __syncthreads();
+        // (B)
+        block_excl_scan<kT>(pref, n0, sc);
     }
-    __syncthreads();
-    // (B)
-    block_excl_scan<kT>(pref, n0, sc);
     const int np = pref[n0];
     // (C) each thread takes a contiguous run of pairs: one search for its
     // first h0, then a forward walk
@@ -875,8 +904,7 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     const int t0 = sc.n_tracks;
     uint64_t* wkey = st.wkey64();
     uint32_t* wc = st.wtmp();
-    if (threadIdx.x == 0) sc.n_acc = 0;
-    __syncthreads();
+    // sc.n_acc was cleared with the plane load
     for (int c = threadIdx.x; c < sc.n_cand; c += kT) {
         if (st.calive(c) == 3) {
             st.calive(c) = 0;
@@ -887,24 +915,19 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     const int nw = sc.n_acc;
     if (t0 + nw > st.cap_tracks()) return false;
     if (nw == 0) return true;
-    uint32_t* rank = wc + nw;
     for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
         wkey[i] = ((uint64_t)__float_as_uint(st.cq(c)) << 32) | (uint32_t)st.L(s0, st.cp(c, 0));
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nw; i += kT) {
-        const uint64_t ki = wkey[i];
-        int r = 0;
-        for (int j = 0; j < nw; ++j) r += wkey[j] < ki ? 1 : 0;
-        rank[i] = (uint32_t)r;
-    }
-    __syncthreads();
-    st.dbase = t0;  // downstream state overlays the winner keys from here on
+    st.dbase = t0;  // downstream state overlays the seeding slots from here on
     st.dn = nw;
     for (int i = threadIdx.x; i < nw; i += kT) {
         const int c = (int)wc[i];
-        const int t = t0 + (int)rank[i];
+        const uint64_t ki = wkey[i];
+        int rk = 0;
+        for (int j = 0; j < nw; ++j) rk += wkey[j] < ki ? 1 : 0;
+        const int t = t0 + rk;
         const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
         const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
         const float x1 = st.X(s1, i1), y1 = st.Y(s1, i1);
@@ -929,7 +952,6 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
         ch[k + 1] = (int32_t)st.ID(s1, i1);
         ch[k + 2] = (int32_t)st.ID(s2, i2);
     }
-    __syncthreads();
     if (threadIdx.x == 0) sc.n_tracks = t0 + nw;
     __syncthreads();
 
