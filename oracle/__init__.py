@@ -136,6 +136,20 @@ def fit(trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, plane_z, sigma, fp64=Tru
     return par[:T]
 
 
+def kalman(trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, plane_z, sigma, ms, fp64=True):
+    """Kalman fits of CSR tracks: [T, 16] = x, y, tx, ty, z, Cxx, Cxt, Ctt, Cyy, Cyt, Ctt, chi2, ndof, 0, 0, 0."""
+    trk_hit_off = np.ascontiguousarray(trk_hit_off, np.int32)
+    T = trk_hit_off.size - 1
+    out = np.zeros((max(T, 1), 16), np.float64)
+    lib().vo_kalman(C.c_longlong(T), _p(trk_hit_off), _p(np.ascontiguousarray(trk_hit, np.int32)),
+                    _p(np.ascontiguousarray(trk_planes, np.uint32)),
+                    _p(np.ascontiguousarray(clu_x, np.float32)),
+                    _p(np.ascontiguousarray(clu_y, np.float32)),
+                    _p(np.ascontiguousarray(plane_z, np.float32)), C.c_float(sigma), C.c_float(ms),
+                    C.c_int(1 if fp64 else 0), _p(out))
+    return out[:T]
+
+
 def standardize(feat, norm):
     feat = np.ascontiguousarray(feat, np.float32)
     out = np.zeros((feat.shape[0], 16), np.uint16)

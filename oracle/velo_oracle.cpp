@@ -420,9 +420,113 @@ std::vector<Track> find_event(const EventIn& ev, const vo_cuts& c, StepStats& st
     return tr;
 }
 
+// Kalman filter of one projection (x or y) of a straight VELO track whose
+// slope receives an independent kick of variance ms2 at every plane it
+// crosses (the parameterised multiple-scattering noise), measurements of
+// variance sigma2.  pl[0..n) are the hit planes ascending, u[] the measured
+// coordinates, zp[] the plane positions.  The filter runs from the most
+// downstream hit towards the interaction region and returns the state at the
+// most upstream hit: position, slope of the segment just downstream of it,
+// their covariance, and the chi2 of the measurements after the first two.
+template <typename T>
+struct KalState { T x, s, cxx, cxs, css, chi2; };
+
+template <typename T>
+KalState<T> kalman_1d(int n, const int* pl, const T* u, const T* zp, T sigma2, T ms2) {
+    KalState<T> k{};
+    if (n < 2) return k;
+    // start at the second most downstream hit b from the two most downstream
+    // hits (a, b): slope (u_a - u_b) / D; the kicks on the planes strictly
+    // between them move u_a by kick * (z_a - z_q)
+    const int a = n - 1, b = n - 2;
+    const T D = zp[pl[a]] - zp[pl[b]];
+    T g = T(0);
+    for (int q = pl[b] + 1; q < pl[a]; ++q) {
+        const T w = (zp[pl[a]] - zp[q]) / D;
+        g = g + w * w;
+    }
+    k.x = u[b];
+    k.s = (u[a] - u[b]) / D;
+    k.cxx = sigma2;
+    k.cxs = -sigma2 / D;
+    k.css = (sigma2 + sigma2) / (D * D) + ms2 * g;
+    k.chi2 = T(0);
+    int p = pl[b];
+    for (int i = b - 1; i >= 0; --i) {
+        // one plane at a time towards the next hit: undo the kick of plane p
+        // (the slope below p differs from the one above it by that kick), then
+        // carry the position down with that slope
+        while (p > pl[i]) {
+            const T dz = zp[p] - zp[p - 1];
+            k.css = k.css + ms2;
+            k.x = k.x - k.s * dz;
+            const T cxx = k.cxx - dz * k.cxs - dz * k.cxs + dz * dz * k.css;
+            const T cxs = k.cxs - dz * k.css;
+            k.cxx = cxx;
+            k.cxs = cxs;
+            --p;
+        }
+        // measurement update
+        const T r = u[i] - k.x;
+        const T S = k.cxx + sigma2;
+        const T kx = k.cxx / S, ks = k.cxs / S;
+        k.x = k.x + kx * r;
+        k.s = k.s + ks * r;
+        const T cxx = k.cxx - kx * k.cxx;
+        const T cxs = k.cxs - kx * k.cxs;
+        const T css = k.css - ks * k.cxs;
+        k.cxx = cxx;
+        k.cxs = cxs;
+        k.css = css;
+        k.chi2 = k.chi2 + r * r / S;
+    }
+    return k;
+}
+
+template <typename T>
+void kalman_track(int n, const int* pl, const T* x, const T* y, const T* zp, T sigma, T ms, double* o) {
+    const T s2 = sigma * sigma, m2 = ms * ms;
+    const KalState<T> kx = kalman_1d<T>(n, pl, x, zp, s2, m2);
+    const KalState<T> ky = kalman_1d<T>(n, pl, y, zp, s2, m2);
+    o[0] = kx.x; o[1] = ky.x; o[2] = kx.s; o[3] = ky.s; o[4] = n > 0 ? zp[pl[0]] : T(0);
+    o[5] = kx.cxx; o[6] = kx.cxs; o[7] = kx.css;
+    o[8] = ky.cxx; o[9] = ky.cxs; o[10] = ky.css;
+    o[11] = kx.chi2 + ky.chi2;
+    o[12] = 2 * n - 4;
+    o[13] = o[14] = o[15] = 0.0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Kalman fits (x and y projections) of n_tracks CSR tracks, slope noise `ms`
+// (rad per plane crossed), measurement error `sigma`.  FP64 or FP32.
+// out[t*16 + {0..15}] = x, y, tx, ty, z (state at the most upstream hit),
+// Cxx, Cxt, Ctt (x projection), Cyy, Cyt, Ctt (y), chi2, ndof, 0, 0, 0.
+void vo_kalman(long long n_tracks, const int32_t* trk_hit_off, const int32_t* trk_hit,
+               const uint32_t* trk_planes, const float* clu_x, const float* clu_y,
+               const float* plane_z, float sigma, float ms, int fp64, double* out) {
+    double zd[kPlanes];
+    for (int k = 0; k < kPlanes; ++k) zd[k] = plane_z[k];
+    for (long long t = 0; t < n_tracks; ++t) {
+        const int a = trk_hit_off[t], n = trk_hit_off[t + 1] - a;
+        int pl[kPlanes];
+        double xd[kPlanes], yd[kPlanes];
+        float xf[kPlanes], yf[kPlanes];
+        int i = 0;
+        for (int k = 0; k < kPlanes && i < n; ++k) {
+            if (!((trk_planes[t] >> k) & 1u)) continue;
+            const int h = trk_hit[a + i];
+            pl[i] = k;
+            xf[i] = clu_x[h]; yf[i] = clu_y[h];
+            xd[i] = xf[i]; yd[i] = yf[i];
+            ++i;
+        }
+        if (fp64) kalman_track<double>(n, pl, xd, yd, zd, double(sigma), double(ms), out + 16 * t);
+        else kalman_track<float>(n, pl, xf, yf, plane_z, sigma, ms, out + 16 * t);
+    }
+}
 
 // Straight-line fits of n_tracks CSR tracks.  FP64 (`fp64`=1) or FP32 (`fp64`=0).
 // par[t*8 + {0..7}] = x_ref, y_ref, z_ref, tx, ty, chi2, ndof, 0 (as double).
