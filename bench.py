@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
+    ap.add_argument("--kalman", type=float, default=None, metavar="MS",
+                    help="also run velo_kalman_fit on each step's tracks (slope noise per plane, rad)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB 3 times (a known-size kernel that "
                          "scales HBM byte counters read by a profiler)")
@@ -163,7 +165,19 @@ def main():
     torch.cuda.synchronize()
     log(f"launch {v.get_launch()}, warm-up")
 
-    step = v.pipeline if args.path == "fused" else v.three_call
+    path_step = v.pipeline if args.path == "fused" else v.three_call
+    kal_out = None
+    if args.kalman is not None:
+        kal_out = torch.empty((max(bufs["trk_cap"], 1), 16), dtype=torch.float32, device=v.device)
+
+    def kalman():
+        v.kalman_fit(bufs["trk_hit_off"], bufs["trk_hit"], bufs["trk_planes"], bufs["clu_x"], bufs["clu_y"],
+                     args.kalman, max_tracks=bufs["trk_cap"], d_n_tracks=bufs["trk_off"][E:], out=kal_out)
+
+    def step(o, i, b):
+        path_step(o, i, b)
+        if kal_out is not None:
+            kalman()
     for _ in range(args.warmup):
         step(off, ids, bufs)
     torch.cuda.synchronize()
@@ -201,6 +215,20 @@ def main():
         acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
     v.set_timing(False)
     stages = {k: acc[k] / args.steps for k in acc}
+    kal = None
+    if kal_out is not None:  # the Kalman fit alone, HIP events on the stream it runs on
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kalman()
+        e0.record()
+        for _ in range(args.steps):
+            kalman()
+        e1.record()
+        torch.cuda.synchronize()
+        kms = e0.elapsed_time(e1) / args.steps
+        stages["kalman"] = kms
+        kbytes = 12 * H + 72 * T  # hit index + x, y per hit; offset, planes, 16-float state per track
+        kal = {"ms": kms, "alg_bytes": kbytes, "achieved_GBs": kbytes / (kms * 1e-3) / 1e9,
+               "frac": kbytes / (kms * 1e-3) / (HBM_PEAK_GBS * 1e9), "ms_noise": args.kalman}
     dom = max(("cluster", "find_lds", "find_large", "accept", "output_fit"), key=lambda k: stages[k])
     # algorithmic bytes per launch (minimum traffic the stage must move)
     n_pix = batch.n_pix
@@ -235,6 +263,7 @@ def main():
             "tracks_per_event": T / E,
             "mode": args.mode,
             "path": args.path,
+            "kalman_ms": args.kalman,
             "launch": {"threads_per_event": th, "tile": tl},
             "autotune_ms": tune_ms,
         },
@@ -253,6 +282,7 @@ def main():
         },
         "path_hbm_frac": path_bytes / E * value / (HBM_PEAK_GBS * 1e9),
         "stages_ms": stages,
+        "kalman": kal,
         "cpu_baseline": cpu,
     }
     if args.calib_copy_mib > 0:

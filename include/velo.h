@@ -151,6 +151,23 @@ int velo_fit(velo_ctx* ctx, int64_t max_tracks, const int32_t* d_n_tracks, const
              const int32_t* d_trk_hit, const uint32_t* d_trk_planes, const float* d_clu_x,
              const float* d_clu_y, float* d_par, void* stream);
 
+/* Kalman fit of the VELO segment (the paper's HLT1 fits only the VELO part of
+ * a track, with a parameterised Kalman filter -- section "HLT1 details and
+ * results"; the parameterisation here is this library's reading): per
+ * projection a straight line whose slope takes an independent kick of
+ * standard deviation `ms` (rad) on every plane crossed, hits with the
+ * context's measurement error sigma.  Started from the two most downstream
+ * hits, run plane by plane towards the interaction region; ms = 0 gives the
+ * least-squares line.
+ *   d_n_tracks (nullable): device count of tracks, as for velo_fit.
+ *   out: d_out[max_tracks][16] = x, y, tx, ty, z (state at the most upstream
+ *   hit; tx, ty = slopes of the segment just downstream of it), Cxx, Cxt, Ctt,
+ *   Cyy, Cyt, Ctt (covariances of the two projections), chi2, ndof, 0, 0, 0.
+ * Errors: VELO_ERR_ARG for a negative or non-finite ms, null arrays. */
+int velo_kalman_fit(velo_ctx* ctx, int64_t max_tracks, const int32_t* d_n_tracks, const int32_t* d_trk_hit_off,
+                    const int32_t* d_trk_hit, const uint32_t* d_trk_planes, const float* d_clu_x,
+                    const float* d_clu_y, float ms, float* d_out, void* stream);
+
 /* The whole path (cluster -> find -> fit) in one call.  Output identical to
  * velo_cluster + velo_find_tracks + velo_fit.  The kernels are captured into a
  * HIP graph on first use for a given argument set and replayed afterwards. */

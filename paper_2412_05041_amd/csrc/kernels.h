@@ -73,6 +73,20 @@ struct FitArgs {
     Params p;
 };
 
+struct KalmanArgs {
+    int64_t max_tracks;
+    const int32_t* n_tracks;  // nullable
+    const int32_t* trk_hit_off;
+    const int32_t* trk_hit;
+    const uint32_t* trk_planes;
+    const float* clu_x;
+    const float* clu_y;
+    float* out;               // [max_tracks][16]
+    float z[kPlanes];
+    float sigma;              // measurement error (mm)
+    float ms;                 // slope kick per plane crossed (rad)
+};
+
 // launchers (return hipError_t)
 hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_t s);
 hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s);
@@ -84,5 +98,6 @@ hipError_t launch_accept(const FindArgs& a, hipStream_t s);
 hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, hipStream_t s);
+hipError_t launch_kalman(const KalmanArgs& a, hipStream_t s);
 
 }  // namespace velo

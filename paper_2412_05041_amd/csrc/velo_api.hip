@@ -422,6 +422,31 @@ int velo_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const int
     return VELO_OK;
 }
 
+int velo_kalman_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const int32_t* trk_hit_off,
+                    const int32_t* trk_hit, const uint32_t* trk_planes, const float* clu_x, const float* clu_y,
+                    float ms, float* out, void* stream) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (max_tracks < 0) return fail(VELO_ERR_ARG, "max_tracks < 0");
+    if (!(ms >= 0.0f) || !std::isfinite(ms)) return fail(VELO_ERR_ARG, "ms must be finite and >= 0");
+    if (max_tracks == 0) return VELO_OK;
+    if (!trk_hit_off || !trk_hit || !trk_planes || !clu_x || !clu_y || !out)
+        return fail(VELO_ERR_ARG, "null argument");
+    KalmanArgs a{};
+    a.max_tracks = max_tracks;
+    a.n_tracks = n_tracks;
+    a.trk_hit_off = trk_hit_off;
+    a.trk_hit = trk_hit;
+    a.trk_planes = trk_planes;
+    a.clu_x = clu_x;
+    a.clu_y = clu_y;
+    a.out = out;
+    for (int k = 0; k < kPlanes; ++k) a.z[k] = c->p.z[k];
+    a.sigma = c->p.sigma;
+    a.ms = ms;
+    HIP_OK(launch_kalman(a, (hipStream_t)stream));
+    return VELO_OK;
+}
+
 int velo_pipeline(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t* pix_id, int32_t* pix_clu,
                   int32_t* clu_off, float* clu_x, float* clu_y, int64_t clu_cap, int32_t* trk_off,
                   int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes, uint8_t* trk_flags,

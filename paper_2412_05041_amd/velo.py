@@ -46,6 +46,7 @@ _SIGS = {
     "velo_find_tracks": [C.c_void_p, C.c_int32] + [C.c_void_p] * 9 + [C.c_int64, C.c_int64, C.c_int32,
                                                                         C.c_void_p, C.c_void_p],
     "velo_fit": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
+    "velo_kalman_fit": [C.c_void_p, C.c_int64] + [C.c_void_p] * 6 + [C.c_float, C.c_void_p, C.c_void_p],
     "velo_pipeline": [C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_int64] + [C.c_void_p] * 7 +
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
@@ -204,6 +205,17 @@ class Velo:
         _check(lib().velo_fit(self.h, int(max_tracks), _ptr(d_n_tracks), _ptr(trk_hit_off), _ptr(trk_hit),
                               _ptr(trk_planes), _ptr(clu_x), _ptr(clu_y), _ptr(par), _stream()))
         return par
+
+    def kalman_fit(self, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, ms, n_tracks=None, max_tracks=None,
+                   d_n_tracks=None, out=None):
+        """Kalman fits [max_tracks, 16] (see velo_kalman_fit)."""
+        if max_tracks is None:
+            max_tracks = trk_hit_off.numel() - 1 if n_tracks is None else n_tracks
+        if out is None:
+            out = torch.zeros((max(max_tracks, 1), 16), dtype=torch.float32, device=self.device)
+        _check(lib().velo_kalman_fit(self.h, int(max_tracks), _ptr(d_n_tracks), _ptr(trk_hit_off), _ptr(trk_hit),
+                                     _ptr(trk_planes), _ptr(clu_x), _ptr(clu_y), float(ms), _ptr(out), _stream()))
+        return out
 
     def pipeline_buffers(self, n_events, n_pix, clu_cap=None, trk_cap=None, hit_cap=None):
         clu_cap = n_pix if clu_cap is None else clu_cap
