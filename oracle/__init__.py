@@ -52,6 +52,7 @@ def lib():
     if _lib is None:
         _lib = C.CDLL(build())
         _lib.vo_cluster.restype = C.c_longlong
+        _lib.vo_decode.restype = C.c_longlong
         _lib.vo_find_tracks.restype = C.c_longlong
         _lib.vo_mlp_loss_grad.restype = C.c_double
         _lib.vo_to_bf16.restype = C.c_uint16
@@ -148,6 +149,19 @@ def kalman(trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, plane_z, sigma, ms, f
                     _p(np.ascontiguousarray(plane_z, np.float32)), C.c_float(sigma), C.c_float(ms),
                     C.c_int(1 if fp64 else 0), _p(out))
     return out[:T]
+
+
+def decode(bank_off, bank, n_events, pix_cap=None):
+    """Super-pixel banks -> (pix_off [E*26+1], pix_id sorted per plane, event flags, total)."""
+    bank_off = np.ascontiguousarray(bank_off, np.int32)
+    bank = np.ascontiguousarray(bank, np.uint32)
+    cap = 8 * bank.size if pix_cap is None else pix_cap
+    pix_off = np.zeros(n_events * 26 + 1, np.int32)
+    pix_id = np.zeros(max(cap, 1), np.uint32)
+    flags = np.zeros(max(n_events, 1), np.int32)
+    total = lib().vo_decode(C.c_int(n_events), _p(bank_off), _p(bank), _p(pix_off), _p(pix_id),
+                            C.c_longlong(cap), _p(flags))
+    return pix_off, pix_id[:min(total, cap)], flags[:n_events], int(total)
 
 
 def standardize(feat, norm):

@@ -500,6 +500,51 @@ void kalman_track(int n, const int* pl, const T* x, const T* y, const T* zp, T s
 
 extern "C" {
 
+// Decode of super-pixel banks into the CSR pixel input (the synthetic raw-bank
+// format: word = pattern[0:8] | sp_row[8:17] | sp_col[17:27], bits 27..31
+// zero; pattern bit 2*dr + dc is pixel (4*sp_row + dr, 2*sp_col + dc)).
+// A word with a reserved bit set, an empty pattern, or a set bit outside the
+// 1454 x 1454 sensor is malformed: it yields no pixel and flags its event (2).
+// A pixel id decoded twice is kept (twice) and flags its event (2).  Each
+// plane's ids are written sorted ascending.  pix_off[E*26+1]; pix_id holds
+// up to pix_cap ids (beyond it only the offsets are written and the event is
+// flagged 1).  Returns the total pixel count.
+long long vo_decode(int n_events, const int32_t* bank_off, const uint32_t* bank, int32_t* pix_off,
+                    uint32_t* pix_id, long long pix_cap, int32_t* flags) {
+    const int n_seg = n_events * kPlanes;
+    for (int e = 0; e < n_events; ++e) flags[e] = 0;
+    long long total = 0;
+    pix_off[0] = 0;
+    for (int sgi = 0; sgi < n_seg; ++sgi) {
+        const int e = sgi / kPlanes;
+        std::vector<uint32_t> ids;
+        for (int wi = bank_off[sgi]; wi < bank_off[sgi + 1]; ++wi) {
+            const uint32_t w = bank[wi];
+            const uint32_t pattern = w & 0xffu, spr = (w >> 8) & 0x1ffu, spc = (w >> 17) & 0x3ffu;
+            bool ok = (w >> 27) == 0 && pattern != 0;
+            std::vector<uint32_t> mine;
+            for (int bit = 0; bit < 8 && ok; ++bit) {
+                if (!((pattern >> bit) & 1u)) continue;
+                const uint32_t r = 4 * spr + (uint32_t)(bit >> 1), c = 2 * spc + (uint32_t)(bit & 1);
+                if (r >= (uint32_t)kSide || c >= (uint32_t)kSide) ok = false;
+                else mine.push_back(r * (uint32_t)kSide + c);
+            }
+            if (!ok) { flags[e] = 2; continue; }
+            ids.insert(ids.end(), mine.begin(), mine.end());
+        }
+        std::sort(ids.begin(), ids.end());
+        for (size_t i = 1; i < ids.size(); ++i)
+            if (ids[i] == ids[i - 1]) flags[e] = 2;
+        for (size_t i = 0; i < ids.size(); ++i) {
+            if (total + (long long)i < pix_cap) pix_id[total + (long long)i] = ids[i];
+        }
+        if (total + (long long)ids.size() > pix_cap && flags[e] == 0) flags[e] = 1;
+        total += (long long)ids.size();
+        pix_off[sgi + 1] = (int32_t)total;
+    }
+    return total;
+}
+
 // Kalman fits (x and y projections) of n_tracks CSR tracks, slope noise `ms`
 // (rad per plane crossed), measurement error `sigma`.  FP64 or FP32.
 // out[t*16 + {0..15}] = x, y, tx, ty, z (state at the most upstream hit),

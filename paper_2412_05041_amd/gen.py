@@ -291,6 +291,44 @@ def generate(w: Workload, max_tracks_per_chunk: int = 300_000) -> Batch:
                  np.concatenate(params) if params else np.zeros((0, 5)), zs)
 
 
+# ---------------------------------------------------------------- raw banks
+# A synthetic front-end format (the paper names the persisted "raw banks" but
+# gives no format; this one is this project's): per (event, plane) a list of
+# 32-bit super-pixel words, each a 2-column x 4-row pixel block --
+#   bits  0..7   hit pattern, bit (2 * row_offset + column_offset)
+#   bits  8..16  super-pixel row    = row >> 2     (0..363)
+#   bits 17..26  super-pixel column = column >> 1  (0..726)
+#   bits 27..31  zero
+# in arbitrary order within the plane (here: a seeded shuffle).
+
+SP_ROWS = (N_SIDE + 3) // 4
+SP_COLS = (N_SIDE + 1) // 2
+
+
+def raw_banks(b: Batch, seed: int = 0):
+    """Encode a batch's pixels as super-pixel words: (bank_off int32 [E*26+1], bank uint32)."""
+    rng = np.random.default_rng(seed)
+    n_seg = b.n_events * N_PLANES
+    seg = np.repeat(np.arange(n_seg, dtype=np.int64), np.diff(b.pix_off.astype(np.int64)))
+    ids = b.pix_id.astype(np.int64)
+    r, c = ids // N_SIDE, ids % N_SIDE
+    spkey = (seg << 20) | ((r >> 2) << 10) | (c >> 1)
+    bit = np.left_shift(1, (r & 3) * 2 + (c & 1))
+    order = np.argsort(spkey, kind="stable")
+    sk, bt = spkey[order], bit[order]
+    first = np.ones(sk.size, bool)
+    first[1:] = sk[1:] != sk[:-1]
+    starts = np.flatnonzero(first)
+    keys = sk[starts]
+    pattern = np.bitwise_or.reduceat(bt, starts) if starts.size else np.zeros(0, np.int64)
+    wseg = keys >> 20
+    words = pattern | (((keys >> 10) & 0x3ff) << 8) | ((keys & 0x3ff) << 17)
+    shuffle = np.lexsort((rng.random(words.size), wseg))
+    words, wseg = words[shuffle], wseg[shuffle]
+    bank_off = np.searchsorted(wseg, np.arange(n_seg + 1)).astype(np.int32)
+    return bank_off, words.astype(np.uint32)
+
+
 def hand_event(tracks, plane_list=None, zs=None, noise=()):
     """Build a one-event batch from explicit straight tracks (tests).
 
