@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
+    ap.add_argument("--raw", action="store_true",
+                    help="start each step from super-pixel raw banks: velo_decode, then the path")
     ap.add_argument("--kalman", type=float, default=None, metavar="MS",
                     help="also run velo_kalman_fit on each step's tracks (slope noise per plane, rad)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -174,7 +176,19 @@ def main():
         v.kalman_fit(bufs["trk_hit_off"], bufs["trk_hit"], bufs["trk_planes"], bufs["clu_x"], bufs["clu_y"],
                      args.kalman, max_tracks=bufs["trk_cap"], d_n_tracks=bufs["trk_off"][E:], out=kal_out)
 
+    dec = None
+    if args.raw:
+        bank_off, bank = gen.raw_banks(batch, seed=w.seed)
+        d_bank_off = torch.from_numpy(bank_off).to(v.device)
+        d_bank = torch.from_numpy(bank.view(np.int32)).to(v.device)
+        dec = v.decode(d_bank_off, d_bank, batch.n_pix)
+        dec_ids = dec["pix_id"][:batch.n_pix]
+        log(f"raw banks: {bank.size} words for {batch.n_pix} pixels")
+
     def step(o, i, b):
+        if dec is not None:
+            v.decode(d_bank_off, d_bank, batch.n_pix, out=dec)
+            o, i = dec["pix_off"], dec_ids
         path_step(o, i, b)
         if kal_out is not None:
             kalman()
@@ -215,6 +229,15 @@ def main():
         acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
     v.set_timing(False)
     stages = {k: acc[k] / args.steps for k in acc}
+    if dec is not None:  # the decode alone, HIP events on the stream it runs on
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            v.decode(d_bank_off, d_bank, batch.n_pix, out=dec)
+        e1.record()
+        torch.cuda.synchronize()
+        stages["decode"] = e0.elapsed_time(e1) / args.steps
+        assert v.read_status(dec["status"])[0] == 0
     kal = None
     if kal_out is not None:  # the Kalman fit alone, HIP events on the stream it runs on
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -264,6 +287,7 @@ def main():
             "mode": args.mode,
             "path": args.path,
             "kalman_ms": args.kalman,
+            "raw_banks": bool(args.raw),
             "launch": {"threads_per_event": th, "tile": tl},
             "autotune_ms": tune_ms,
         },

@@ -151,6 +151,23 @@ int velo_fit(velo_ctx* ctx, int64_t max_tracks, const int32_t* d_n_tracks, const
              const int32_t* d_trk_hit, const uint32_t* d_trk_planes, const float* d_clu_x,
              const float* d_clu_y, float* d_par, void* stream);
 
+/* Decode of raw banks (a synthetic super-pixel format: the paper names the
+ * persisted raw banks of the detector but not their format) into the CSR
+ * pixel input of velo_cluster.  Per (event, plane) a list of 32-bit words, in
+ * any order, word = pattern[0:8] | sp_row[8:17] | sp_col[17:27] with bits
+ * 27..31 zero; pattern bit 2*dr + dc is the pixel (row 4*sp_row + dr, column
+ * 2*sp_col + dc).
+ *   d_bank_off[n_events*26+1] word offsets, d_bank words (device).
+ *   out: d_pix_off[n_events*26+1], d_pix_id[pix_cap] -- each plane's ids
+ *   sorted ascending.  A plane whose ids do not all fit below pix_cap writes
+ *   none (its event flagged VELO_EV_OVERFLOW; offsets stay complete).
+ * A malformed word (reserved bit, empty pattern, pixel off the sensor) yields
+ * no pixel; it and any pixel decoded twice (kept) flag the event
+ * VELO_EV_BAD_INPUT.  d_status[4] = total pixels.  Needs velo_reserve for
+ * n_events. */
+int velo_decode(velo_ctx* ctx, int32_t n_events, const int32_t* d_bank_off, const uint32_t* d_bank,
+                int32_t* d_pix_off, uint32_t* d_pix_id, int64_t pix_cap, int32_t* d_status, void* stream);
+
 /* Kalman fit of the VELO segment (the paper's HLT1 fits only the VELO part of
  * a track, with a parameterised Kalman filter -- section "HLT1 details and
  * results"; the parameterisation here is this library's reading): per

@@ -507,8 +507,9 @@ extern "C" {
 // 1454 x 1454 sensor is malformed: it yields no pixel and flags its event (2).
 // A pixel id decoded twice is kept (twice) and flags its event (2).  Each
 // plane's ids are written sorted ascending.  pix_off[E*26+1]; pix_id holds
-// up to pix_cap ids (beyond it only the offsets are written and the event is
-// flagged 1).  Returns the total pixel count.
+// up to pix_cap ids: a plane whose ids would not all fit writes none of them
+// and flags its event 1 (the offsets stay complete).  Returns the total pixel
+// count.
 long long vo_decode(int n_events, const int32_t* bank_off, const uint32_t* bank, int32_t* pix_off,
                     uint32_t* pix_id, long long pix_cap, int32_t* flags) {
     const int n_seg = n_events * kPlanes;
@@ -535,10 +536,11 @@ long long vo_decode(int n_events, const int32_t* bank_off, const uint32_t* bank,
         std::sort(ids.begin(), ids.end());
         for (size_t i = 1; i < ids.size(); ++i)
             if (ids[i] == ids[i - 1]) flags[e] = 2;
-        for (size_t i = 0; i < ids.size(); ++i) {
-            if (total + (long long)i < pix_cap) pix_id[total + (long long)i] = ids[i];
+        if (total + (long long)ids.size() <= pix_cap) {
+            for (size_t i = 0; i < ids.size(); ++i) pix_id[total + (long long)i] = ids[i];
+        } else if (flags[e] == 0) {
+            flags[e] = 1;
         }
-        if (total + (long long)ids.size() > pix_cap && flags[e] == 0) flags[e] = 1;
         total += (long long)ids.size();
         pix_off[sgi + 1] = (int32_t)total;
     }

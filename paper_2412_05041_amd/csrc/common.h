@@ -127,6 +127,14 @@ __device__ __forceinline__ void set_event_flag(int32_t* status, int e, int flag,
     atomicMax(status + ST_SEVERITY, severity);
 }
 
+// Synchronisation of the lanes of one wave (they run in lockstep: a fence
+// orders the LDS accesses around the point, no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-wide exclusive prefix sum of v (wave64).
 __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
     int x = v;

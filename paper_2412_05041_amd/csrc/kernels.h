@@ -87,6 +87,17 @@ struct KalmanArgs {
     float ms;                 // slope kick per plane crossed (rad)
 };
 
+struct DecodeArgs {
+    int n_seg;                // events * 26
+    const int32_t* bank_off;  // [n_seg + 1] word offsets
+    const uint32_t* bank;     // super-pixel words
+    int32_t* pix_off;         // [n_seg + 1]
+    uint32_t* pix_id;         // [pix_cap]
+    int64_t pix_cap;
+    int32_t* status;          // nullable
+    Work w;                   // seg_m: per-plane pixel counts
+};
+
 // launchers (return hipError_t)
 hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_t s);
 hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s);
@@ -99,5 +110,6 @@ hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, hipStream_t s);
 hipError_t launch_kalman(const KalmanArgs& a, hipStream_t s);
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t s);
 
 }  // namespace velo

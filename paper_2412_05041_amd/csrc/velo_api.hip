@@ -422,6 +422,27 @@ int velo_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const int
     return VELO_OK;
 }
 
+int velo_decode(velo_ctx* c, int32_t E, const int32_t* bank_off, const uint32_t* bank, int32_t* pix_off,
+                uint32_t* pix_id, int64_t pix_cap, int32_t* status, void* stream) {
+    if (int rc = check_ctx(c)) return rc;
+    if (E < 0 || pix_cap < 0 || !bank_off || !pix_off || (pix_cap > 0 && !pix_id)) return fail(VELO_ERR_ARG, "bad arguments");
+    if (int rc = check_reserved(c, E, 0)) return rc;
+    if (E == 0) return VELO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_reset(c->w, E, status, s));
+    DecodeArgs a{};
+    a.n_seg = E * kPlanes;
+    a.bank_off = bank_off;
+    a.bank = bank;
+    a.pix_off = pix_off;
+    a.pix_id = pix_id;
+    a.pix_cap = pix_cap;
+    a.status = status;
+    a.w = c->w;
+    HIP_OK(launch_decode(a, s));
+    return VELO_OK;
+}
+
 int velo_kalman_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const int32_t* trk_hit_off,
                     const int32_t* trk_hit, const uint32_t* trk_planes, const float* clu_x, const float* clu_y,
                     float ms, float* out, void* stream) {

@@ -47,6 +47,7 @@ _SIGS = {
                                                                         C.c_void_p, C.c_void_p],
     "velo_fit": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
     "velo_kalman_fit": [C.c_void_p, C.c_int64] + [C.c_void_p] * 6 + [C.c_float, C.c_void_p, C.c_void_p],
+    "velo_decode": [C.c_void_p, C.c_int32] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p, C.c_void_p],
     "velo_pipeline": [C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_int64] + [C.c_void_p] * 7 +
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
@@ -205,6 +206,17 @@ class Velo:
         _check(lib().velo_fit(self.h, int(max_tracks), _ptr(d_n_tracks), _ptr(trk_hit_off), _ptr(trk_hit),
                               _ptr(trk_planes), _ptr(clu_x), _ptr(clu_y), _ptr(par), _stream()))
         return par
+
+    def decode(self, bank_off, bank, pix_cap, out=None):
+        """Raw super-pixel banks -> dict(pix_off, pix_id, status) (see velo_decode)."""
+        E = (bank_off.numel() - 1) // N_PLANES
+        if out is None:
+            out = dict(pix_off=self._i32(E * N_PLANES + 1),
+                       pix_id=torch.empty(max(pix_cap, 1), dtype=torch.int32, device=self.device),
+                       status=self.status_buffer(E))
+        _check(lib().velo_decode(self.h, E, _ptr(bank_off), _ptr(bank), _ptr(out["pix_off"]), _ptr(out["pix_id"]),
+                                 int(pix_cap), _ptr(out["status"]), _stream()))
+        return out
 
     def kalman_fit(self, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, ms, n_tracks=None, max_tracks=None,
                    d_n_tracks=None, out=None):

@@ -4,7 +4,8 @@ Pins: the round trip through the generator's encoder (independent numpy code)
 returns the generated pixels exactly; hand-built words decode to the pixels
 their fields name; each malformation (reserved bits, empty pattern, a set bit
 outside the sensor) drops its word and flags its event; a pixel decoded twice
-is kept and flags its event; the capacity limit keeps complete offsets.
+is kept and flags its event; under a capacity limit the planes that fit are
+written, the others not, and the offsets stay complete.
 """
 import numpy as np
 import pytest
@@ -74,7 +75,9 @@ def test_duplicate_pixel_is_kept_and_flagged():
 def test_capacity_keeps_offsets():
     b = gen.generate(gen.WORKLOADS["tiny"].with_events(3, 9))
     off, bank = gen.raw_banks(b)
-    pix_off, pix_id, flags, total = oracle.decode(off, bank, 3, pix_cap=b.n_pix - 5)
+    cap = b.n_pix - 5
+    pix_off, pix_id, flags, total = oracle.decode(off, bank, 3, pix_cap=cap)
     assert total == b.n_pix and np.array_equal(pix_off, b.pix_off)
-    assert np.array_equal(pix_id, b.pix_id[:b.n_pix - 5])
-    assert flags[2] == 1
+    fit = int(b.pix_off[b.pix_off <= cap].max())  # planes that fit entirely are written
+    assert np.array_equal(pix_id[:fit], b.pix_id[:fit])
+    assert flags[2] == 1 and flags[0] == 0
