@@ -1,0 +1,57 @@
+"""What the trained ghost filter gains over the plain chi2 cut (committed weights).
+
+The network in configs/mlp_default.npz was trained on the GPU by the library's
+own kernels (paper_2412_05041_amd/train_filter.py) on candidates of the
+single-vertex generator found with the loose windows.  On independent events
+of that generator it must keep the efficiency target (>= plain - 0.5 %) and,
+there, recover the true tracks the chi2 cut throws away (those carrying one
+stray hit) -- a gain of more than a point -- at a ghost rate still below
+0.5 %.  On nominal events (scattering + noise, the ms cut set) it must keep
+the efficiency target too.
+"""
+import os
+
+import pytest
+
+from paper_2412_05041_amd import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2412_05041_amd import learned, velo
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(learned.WEIGHTS):
+        pytest.skip("no trained weights")
+    master, norm = learned.load_default_weights()
+    return learned, velo, master, norm
+
+
+def test_learned_filter_gain_on_training_like_events(ctx):
+    learned, velo, master, norm = ctx
+    loose = learned.cuts("loose")
+    v = velo.Velo(gen.plane_z(), loose)
+    v.mlp_set_weights(master, norm)
+    test = gen.generate(gen.WORKLOADS["learned_test"].with_events(2000))
+    r = learned.evaluate(v, test, loose, learned.DEFAULT_BAND)
+    p, l = r["plain"], r["learned"]
+    print(f"plain {p['efficiency']:.4f}/{p['ghost_rate']:.5f}  learned {l['efficiency']:.4f}/{l['ghost_rate']:.5f}")
+    assert l["efficiency"] >= p["efficiency"] - 0.005
+    assert l["efficiency"] > p["efficiency"] + 0.01
+    assert l["ghost_rate"] < 0.005
+
+
+def test_learned_filter_keeps_nominal_efficiency(ctx):
+    learned, velo, master, norm = ctx
+    ms = learned.cuts("ms")
+    v = velo.Velo(gen.plane_z(), ms)
+    v.mlp_set_weights(master, norm)
+    nominal = gen.generate(gen.WORKLOADS["nominal"].with_events(200, 9202))
+    r = learned.evaluate(v, nominal, ms, learned.DEFAULT_BAND)
+    p, l = r["plain"], r["learned"]
+    print(f"plain {p['efficiency']:.4f}/{p['ghost_rate']:.5f}  learned {l['efficiency']:.4f}/{l['ghost_rate']:.5f}")
+    assert l["efficiency"] >= p["efficiency"] - 0.005
+    assert l["ghost_rate"] <= p["ghost_rate"] + 0.005
