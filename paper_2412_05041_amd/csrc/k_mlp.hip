@@ -330,14 +330,28 @@ __global__ __launch_bounds__(kGradThreads) void k_mlp_grad(const float* master, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_grad_reduce(const float* part, int nblocks, float* grad, float* loss,
-                                                     float inv_n) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > kNParam) return;
+// Fixed-order sum of the per-block partials: for 64 consecutive parameters
+// (one per lane), wave w adds the partials of blocks [w*nb/16, (w+1)*nb/16) in
+// block order, then wave 0 adds the 16 wave sums in wave order.  The order
+// depends only on the number of blocks, so the gradient is reproducible.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(kRedWaves * kWave) void k_grad_reduce(const float* part, int nblocks, float* grad,
+                                                                  float* loss, float inv_n) {
+    __shared__ float s_sum[kRedWaves][kWave];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int p = blockIdx.x * kWave + lane;
+    const int b0 = (int)((int64_t)nblocks * wv / kRedWaves), b1 = (int)((int64_t)nblocks * (wv + 1) / kRedWaves);
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kGradStride + p];
-    if (p < kNParam) grad[p] = s;
-    else if (loss) *loss = s * inv_n;
+    if (p <= kNParam)
+        for (int b = b0; b < b1; ++b) s += part[(int64_t)b * kGradStride + p];
+    s_sum[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && p <= kNParam) {
+        float t = 0.0f;
+        for (int w = 0; w < kRedWaves; ++w) t += s_sum[w][lane];
+        if (p < kNParam) grad[p] = t;
+        else if (loss) *loss = t * inv_n;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, const float* g, float lr, float b1,
@@ -449,8 +463,8 @@ hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const u
                        m.d_part, per_wave);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, s, m.d_part, (int)blocks, grad,
-                       loss, 1.0f / (float)n);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kNParam + 1 + kWave - 1) / kWave), dim3(kRedWaves * kWave), 0, s, m.d_part,
+                       (int)blocks, grad, loss, 1.0f / (float)n);
     return hipGetLastError();
 }
 
