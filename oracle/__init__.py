@@ -44,6 +44,18 @@ class Mlp(C.Structure):
     _fields_ = [("master", C.c_void_p), ("norm", C.c_void_p)]
 
 
+class SeedNet(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("norm", C.c_void_p), ("threshold", C.c_float)]
+
+
+def _seed_struct(seed):
+    """(weights[1441], norm[20], threshold) -> (struct, arrays kept alive)."""
+    w = np.ascontiguousarray(seed[0], np.float32)
+    nm = np.ascontiguousarray(seed[1], np.float32)
+    assert w.size == N_PARAM and nm.size == 20
+    return SeedNet(w.ctypes.data, nm.ctypes.data, float(seed[2])), (w, nm)
+
+
 _lib = None
 
 
@@ -86,7 +98,10 @@ def cluster(pix_off, pix_id):
 
 
 def find_tracks(clu_off, clu_x, clu_y, plane_z, cuts: dict, mlp=None, emit_rejected=False,
-                dbg_event=-1, dbg_step=-1):
+                dbg_event=-1, dbg_step=-1, seed=None):
+    """Track finding.  mlp = (master, norm) for the learned acceptance; seed =
+    (weights, norm, threshold) for the seed-level filter.  stats = pair tests,
+    triplet tests, seed candidates, seeds dropped by the seed filter."""
     clu_off = np.ascontiguousarray(clu_off, np.int32)
     clu_x = np.ascontiguousarray(clu_x, np.float32)
     clu_y = np.ascontiguousarray(clu_y, np.float32)
@@ -101,8 +116,9 @@ def find_tracks(clu_off, clu_x, clu_y, plane_z, cuts: dict, mlp=None, emit_rejec
     flags = np.empty(tcap, np.uint8)
     logit = np.empty(tcap, np.float32)
     feat = np.empty((tcap, 10), np.float32)
-    stats = np.zeros(3, np.int64)
+    stats = np.zeros(4, np.int64)
     c = cuts_struct(cuts)
+    seed_s, seed_keep = _seed_struct(seed) if seed is not None else (None, None)
     mlp_s = None
     keep = None
     if mlp is not None:
@@ -112,6 +128,7 @@ def find_tracks(clu_off, clu_x, clu_y, plane_z, cuts: dict, mlp=None, emit_rejec
     dbg_n = np.zeros(1, np.int64)
     T = lib().vo_find_tracks(C.c_int(E), _p(clu_off), _p(clu_x), _p(clu_y), _p(plane_z),
                              C.byref(c), C.byref(mlp_s) if mlp_s is not None else None,
+                             C.byref(seed_s) if seed_s is not None else None,
                              C.c_int(1 if emit_rejected else 0), _p(trk_off), _p(hit_off),
                              _p(hits), _p(planes), _p(flags), _p(logit), _p(feat), _p(stats),
                              C.c_int(dbg_event), C.c_int(dbg_step), _p(dbg_cand), _p(dbg_n))
@@ -121,6 +138,32 @@ def find_tracks(clu_off, clu_x, clu_y, plane_z, cuts: dict, mlp=None, emit_rejec
                trk_logit=logit[:T].copy(), trk_feat=feat[:T].copy(), stats=stats)
     if dbg_cand is not None:
         out["dbg_cand"] = dbg_cand[:int(dbg_n[0])].copy()
+    return out
+
+
+def seed_features(hits, clu_off, clu_x, clu_y, plane_z):
+    """FP32 features [n][10] of seed triplets hits[n][3] (global cluster indices
+    on planes k, k+1, k+2 of one event)."""
+    hits = np.ascontiguousarray(hits, np.int32).reshape(-1, 3)
+    clu_off = np.ascontiguousarray(clu_off, np.int32)
+    clu_x = np.ascontiguousarray(clu_x, np.float32)
+    clu_y = np.ascontiguousarray(clu_y, np.float32)
+    plane_z = np.ascontiguousarray(plane_z, np.float32)
+    E = (clu_off.size - 1) // N_PLANES
+    feat = np.empty((hits.shape[0], 10), np.float32)
+    rc = lib().vo_seed_features(C.c_longlong(hits.shape[0]), _p(hits), C.c_int(E), _p(clu_off), _p(clu_x),
+                                _p(clu_y), _p(plane_z), _p(feat))
+    if rc != 0:
+        raise ValueError("a triplet is not on three consecutive planes of one event")
+    return feat
+
+
+def seed_logit(feat, seed):
+    """FP32 logits of the seed network (weights, norm, threshold) on raw features [n][10]."""
+    feat = np.ascontiguousarray(feat, np.float32).reshape(-1, 10)
+    s, keep = _seed_struct(seed)
+    out = np.empty(feat.shape[0], np.float32)
+    lib().vo_seed_logit(C.c_longlong(feat.shape[0]), _p(feat), C.byref(s), _p(out))
     return out
 
 

@@ -126,6 +126,14 @@ struct vo_cuts {
     float logit_band; // learned: |logit| < band falls back to the plain cut
 };
 
+// Seed-level learned filter: a network of the track filter's shape (10 -> 32
+// -> 32 -> 1) applied to every seed candidate before the claiming.
+struct vo_seed_net {
+    const float* w;     // 1441 FP32 weights, the track network's layout
+    const float* norm;  // 10 means then 10 standard deviations of the features
+    float threshold;    // a candidate whose logit exceeds this is dropped
+};
+
 }  // extern "C"
 
 namespace {
@@ -320,10 +328,75 @@ struct Seed {
 };
 
 struct StepStats {
-    long long pair_tests = 0, triplet_tests = 0, candidates = 0;
+    long long pair_tests = 0, triplet_tests = 0, candidates = 0, rejected = 0;
 };
 
-std::vector<Track> find_event(const EventIn& ev, const vo_cuts& c, StepStats& st,
+// ---------------------------------------------------------------------------
+// Seed-level learned filter (a project extension in the spirit of the paper's
+// remark that the first stage simplifies its pattern recognition for
+// throughput).  Ten FP32 features of a seed (h0, h1, h2) on planes k, k+1,
+// k+2, each written in one fixed order:
+//   0  q, the squared miss of h1 from the line through h0 and h2 (the seed cut)
+//   1  squared transverse distance of that line from the z axis
+//   2  z where the line passes closest to the z axis, clipped to +-2000 mm
+//   3  squared radius of h0
+//   4  squared slope tx^2 + ty^2
+//   5  squared cosine between h0's radial direction and the slope direction
+//   6  k;  7, 8, 9  number of clusters on planes k, k+1, k+2
+// ---------------------------------------------------------------------------
+
+constexpr float kSeedZLim = 2000.0f;
+
+void seed_features(const EventIn& ev, int k, int h0, int h1, int h2, float* f) {
+    const float x0 = ev.x[h0], y0 = ev.y[h0];
+    const float dz2 = ev.z[k + 2] - ev.z[k];
+    const float dz1 = ev.z[k + 1] - ev.z[k];
+    const float tx = (ev.x[h2] - x0) / dz2;
+    const float ty = (ev.y[h2] - y0) / dz2;
+    const float ex = x0 + tx * dz1;
+    const float ey = y0 + ty * dz1;
+    const float dx = ev.x[h1] - ex;
+    const float dy = ev.y[h1] - ey;
+    const float t2 = tx * tx + ty * ty;
+    const float rt = x0 * tx + y0 * ty;
+    const float cr = x0 * ty - y0 * tx;
+    const float r2 = x0 * x0 + y0 * y0;
+    float zc = ev.z[k] - rt / t2;
+    zc = zc < -kSeedZLim ? -kSeedZLim : (zc > kSeedZLim ? kSeedZLim : zc);
+    f[0] = dx * dx + dy * dy;
+    f[1] = cr * cr / t2;
+    f[2] = zc;
+    f[3] = r2;
+    f[4] = t2;
+    f[5] = rt * rt / (r2 * t2);
+    f[6] = float(k);
+    f[7] = float(ev.base[k + 1] - ev.base[k]);
+    f[8] = float(ev.base[k + 2] - ev.base[k + 1]);
+    f[9] = float(ev.base[k + 3] - ev.base[k + 2]);
+}
+
+// The seed network in FP32: standardise, then each unit starts from its bias
+// and adds weight x input for inputs in ascending order; ReLU between layers.
+float seed_logit(const vo_seed_net& sn, const float* f) {
+    const float* w = sn.w;
+    float xs[kIn], h1[kH], h2[kH];
+    for (int i = 0; i < kIn; ++i) xs[i] = (f[i] - sn.norm[i]) / sn.norm[kIn + i];
+    for (int o = 0; o < kH; ++o) {
+        float a = w[oB1 + o];
+        for (int i = 0; i < kIn; ++i) a = a + w[oW1 + o * kIn + i] * xs[i];
+        h1[o] = a > 0.0f ? a : 0.0f;
+    }
+    for (int o = 0; o < kH; ++o) {
+        float a = w[oB2 + o];
+        for (int i = 0; i < kH; ++i) a = a + w[oW2 + o * kH + i] * h1[i];
+        h2[o] = a > 0.0f ? a : 0.0f;
+    }
+    float z = w[oB3];
+    for (int i = 0; i < kH; ++i) z = z + w[oW3 + i] * h2[i];
+    return z;
+}
+
+std::vector<Track> find_event(const EventIn& ev, const vo_cuts& c, const vo_seed_net* sn, StepStats& st,
                               int dbg_step, std::vector<Seed>* dbg_cands) {
     const int n = ev.base[kPlanes];
     std::vector<char> used(n, 0);
@@ -376,6 +449,17 @@ std::vector<Track> find_event(const EventIn& ev, const vo_cuts& c, StepStats& st
             }
         }
         st.candidates += (long long)cand.size();
+        if (sn) {
+            // the seed filter: drop the candidates the network calls fake
+            size_t m = 0;
+            for (const Seed& s : cand) {
+                float f[kIn];
+                seed_features(ev, k, s.h0, s.h1, s.h2, f);
+                if (seed_logit(*sn, f) > sn->threshold) ++st.rejected;
+                else cand[m++] = s;
+            }
+            cand.resize(m);
+        }
         std::sort(cand.begin(), cand.end(), [](const Seed& a, const Seed& b) {
             if (a.q != b.q) return a.q < b.q;
             if (a.h0 != b.h0) return a.h0 < b.h0;
@@ -620,11 +704,12 @@ enum { VO_PLAIN_ACCEPT = 1, VO_LEARNED = 2, VO_FALLBACK = 4, VO_ACCEPT = 8 };
 // trk_off[E+1], trk_hit_off[T+1], trk_hit[H] (global cluster index, plane
 // ascending), trk_planes[T] bitmask, trk_flags[T], trk_logit[T] (nullable),
 // trk_feat[T*10] (nullable, the FP32 features).  emit_rejected=1 outputs every
-// candidate.  stats (nullable): pair tests, triplet tests, seed candidates.
+// candidate.  seed (nullable): the seed-level filter.  stats (nullable): pair
+// tests, triplet tests, seed candidates, seeds dropped by the seed filter.
 // Returns the number of tracks written.
 long long vo_find_tracks(int n_events, const int32_t* clu_off, const float* clu_x,
                          const float* clu_y, const float* plane_z, const vo_cuts* cuts,
-                         const vo_mlp* mlp, int emit_rejected, int32_t* trk_off,
+                         const vo_mlp* mlp, const vo_seed_net* seed, int emit_rejected, int32_t* trk_off,
                          int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes,
                          uint8_t* trk_flags, float* trk_logit, float* trk_feat,
                          long long* stats, int dbg_event, int dbg_step, float* dbg_cand,
@@ -642,7 +727,7 @@ long long vo_find_tracks(int n_events, const int32_t* clu_off, const float* clu_
         ev.z = plane_z;
         std::vector<Seed> dc;
         const bool dbg = dbg_cand && e == dbg_event;
-        std::vector<Track> tr = find_event(ev, *cuts, st, dbg ? dbg_step : -1, dbg ? &dc : nullptr);
+        std::vector<Track> tr = find_event(ev, *cuts, seed, st, dbg ? dbg_step : -1, dbg ? &dc : nullptr);
         if (dbg) {
             for (size_t i = 0; i < dc.size(); ++i) {
                 dbg_cand[4 * i] = dc[i].q;
@@ -699,8 +784,42 @@ long long vo_find_tracks(int n_events, const int32_t* clu_off, const float* clu_
         }
         trk_off[e + 1] = int32_t(T);
     }
-    if (stats) { stats[0] = st.pair_tests; stats[1] = st.triplet_tests; stats[2] = st.candidates; }
+    if (stats) {
+        stats[0] = st.pair_tests;
+        stats[1] = st.triplet_tests;
+        stats[2] = st.candidates;
+        stats[3] = st.rejected;
+    }
     return T;
+}
+
+// Seed features of given triplets: hits[n][3] are global cluster indices on
+// planes k, k+1, k+2 of one event.  Returns 0, or -1 (nothing written past the
+// offending row) when a triplet is not on three consecutive planes of one event.
+int vo_seed_features(long long n, const int32_t* hits, int n_events, const int32_t* clu_off,
+                     const float* clu_x, const float* clu_y, const float* plane_z, float* feat) {
+    const int32_t* end = clu_off + n_events * kPlanes + 1;
+    for (long long t = 0; t < n; ++t) {
+        const int32_t* h = hits + 3 * t;
+        const long long s = (long long)(std::upper_bound(clu_off, end, h[0]) - clu_off) - 1;
+        if (s < 0 || s >= (long long)n_events * kPlanes) return -1;
+        const int e = int(s / kPlanes), k = int(s % kPlanes);
+        if (k > kPlanes - 3) return -1;
+        const int32_t* o = clu_off + e * kPlanes;
+        if (!(h[1] >= o[k + 1] && h[1] < o[k + 2] && h[2] >= o[k + 2] && h[2] < o[k + 3])) return -1;
+        EventIn ev;
+        for (int j = 0; j <= kPlanes; ++j) ev.base[j] = o[j] - o[0];
+        ev.x = clu_x + o[0];
+        ev.y = clu_y + o[0];
+        ev.z = plane_z;
+        seed_features(ev, k, h[0] - o[0], h[1] - o[0], h[2] - o[0], feat + kIn * t);
+    }
+    return 0;
+}
+
+// Logits of the seed network for given raw features [n][10].
+void vo_seed_logit(long long n, const float* feat, const vo_seed_net* sn, float* out) {
+    for (long long t = 0; t < n; ++t) out[t] = seed_logit(*sn, feat + kIn * t);
 }
 
 // Standardised BF16 features of given FP32 features (row-major [n][10]) -> [n][16].
