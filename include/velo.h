@@ -254,6 +254,35 @@ int velo_mlp_set_adam(velo_ctx* ctx, float beta1, float beta2, float eps);
 int velo_mlp_get_state(velo_ctx* ctx, float* h_master, float* h_m, float* h_v, int64_t* h_step);
 int velo_mlp_set_state(velo_ctx* ctx, const float* h_master, const float* h_m, const float* h_v, int64_t step);
 
+/* Seed-level learned filter (a triplet filter: an extension of the simplified
+ * pattern recognition that the first trigger stage uses for throughput --
+ * section "HLT1 details and results" -- with the track filter's network
+ * shape).  Every seed candidate that passes the
+ * seed cuts gets ten FP32 features: the middle-hit miss q, the squared
+ * transverse distance of the h0-h2 line from the z axis, the z of its closest
+ * approach to the axis (clipped to +-2000 mm), h0's squared radius, the squared
+ * slope, the squared cosine between h0's radial direction and the slope, the
+ * plane k and the cluster counts of planes k, k+1, k+2.  The network runs in
+ * FP32 (bias first, inputs ascending, ReLU; no BF16 rounding), and a candidate
+ * whose logit exceeds `threshold` is dropped before the claiming, which changes
+ * the tracks found.  h_weights: 1441 floats in the track network's order
+ * (pass BF16-rounded values to reproduce a BF16-trained network); h_norm: 10
+ * means then 10 non-zero standard deviations; both copied (host pointers).
+ * h_weights = NULL switches the filter off (the default).  Applies to
+ * velo_find_tracks, velo_pipeline and velo_autotune from the next call. */
+int velo_seed_filter_set(velo_ctx* ctx, const float* h_weights, const float* h_norm, float threshold);
+
+/* Training emission of seed candidates: from the next finder call on, every
+ * candidate reaching the seed filter (all that pass the seed cuts) appends
+ * its ten raw features to d_feat [cap][10] (FP32) and its three global cluster
+ * indices (planes k, k+1, k+2) to d_hits [cap][3]; *d_count (caller-zeroed
+ * device counter) counts all of them, also those beyond `cap`, which are not
+ * written.  Order is unspecified, and an event that the LDS-tile finder hands
+ * on to the large-event finder may emit some candidates twice.  All NULL
+ * switches emission off.  The buffers are caller-owned and must stay valid
+ * while emission is on. */
+int velo_seed_emit(velo_ctx* ctx, float* d_feat, int32_t* d_hits, int64_t cap, unsigned long long* d_count);
+
 /* Synchronises `stream` and copies `n_words` status words to the host. */
 int velo_status_read(velo_ctx* ctx, const int32_t* d_status, int32_t* h_status, int32_t n_words, void* stream);
 

@@ -101,7 +101,9 @@ def find_tracks(clu_off, clu_x, clu_y, plane_z, cuts: dict, mlp=None, emit_rejec
                 dbg_event=-1, dbg_step=-1, seed=None):
     """Track finding.  mlp = (master, norm) for the learned acceptance; seed =
     (weights, norm, threshold) for the seed-level filter.  stats = pair tests,
-    triplet tests, seed candidates, seeds dropped by the seed filter."""
+    triplet tests, seed candidates, seeds dropped by the seed filter.
+    dbg_event/dbg_step: the seed candidates (q, h0, h1, h2; event-local, after
+    the seed filter, sorted) of one step of one event; dbg_step=-2 all steps."""
     clu_off = np.ascontiguousarray(clu_off, np.int32)
     clu_x = np.ascontiguousarray(clu_x, np.float32)
     clu_y = np.ascontiguousarray(clu_y, np.float32)

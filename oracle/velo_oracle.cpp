@@ -467,6 +467,7 @@ std::vector<Track> find_event(const EventIn& ev, const vo_cuts& c, const vo_seed
             return a.h2 < b.h2;
         });
         if (dbg_cands && dbg_step == k) *dbg_cands = cand;
+        if (dbg_cands && dbg_step == -2) dbg_cands->insert(dbg_cands->end(), cand.begin(), cand.end());
         const int first_new = int(tr.size());
         for (const Seed& s : cand) {
             if (used[s.h0] || used[s.h1] || used[s.h2]) continue;
@@ -726,7 +727,7 @@ long long vo_find_tracks(int n_events, const int32_t* clu_off, const float* clu_
         ev.y = clu_y + g0;
         ev.z = plane_z;
         std::vector<Seed> dc;
-        const bool dbg = dbg_cand && e == dbg_event;
+        const bool dbg = dbg_cand && e == dbg_event;  // dbg_step -2: every step's candidates
         std::vector<Track> tr = find_event(ev, *cuts, seed, st, dbg ? dbg_step : -1, dbg ? &dc : nullptr);
         if (dbg) {
             for (size_t i = 0; i < dc.size(); ++i) {

@@ -19,6 +19,16 @@ constexpr int64_t kCellWords = (int64_t)26 * (kCells + 1) + kCells;  // per work
 constexpr int kMaxLdsBlocksPerCu = 8;  // bound of the LDS-tile finder's grid
 constexpr int kLutSmall = 256;         // key buckets of an LDS-tile plane
 constexpr int kWave = 64;
+
+// Seed-level filter network (10 -> 32 -> 32 -> 1) as the finder reads it: the
+// first two weight matrices transposed ([input][unit], so the 32 lanes of a
+// half-wave read one row), biases, output weights, the feature normalisation
+// (10 means, 10 standard deviations) and the rejection threshold.
+constexpr int kSeedIn = 10, kSeedH = 32;
+constexpr int kSeedW1T = 0, kSeedB1 = kSeedW1T + kSeedIn * kSeedH, kSeedW2T = kSeedB1 + kSeedH,
+              kSeedB2 = kSeedW2T + kSeedH * kSeedH, kSeedW3 = kSeedB2 + kSeedH, kSeedB3 = kSeedW3 + kSeedH,
+              kSeedNorm = kSeedB3 + 1, kSeedThr = kSeedNorm + 2 * kSeedIn, kSeedFloats = kSeedThr + 1;
+constexpr float kSeedZLim = 2000.0f;  // clip of the closest-approach z feature (mm)
 constexpr int kKeyBits = 16;          // azimuth key resolution
 constexpr int kBuckets = 1024;        // counting-sort buckets of large segments (top 10 key bits)
 

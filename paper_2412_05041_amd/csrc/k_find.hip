@@ -1010,9 +1010,87 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
     return true;
 }
 
+// Seed-level learned filter and training emission, between enumeration and
+// claiming.  A half-wave (32 lanes) takes one candidate: every lane forms its
+// ten features, lane o evaluates hidden unit o of both layers with the inputs
+// broadcast across the half-wave, and every lane sums the output unit.  A
+// candidate whose logit exceeds the threshold dies.  FP32 in a fixed order:
+// each unit starts from its bias and adds weight x input, inputs ascending.
+template <int kT, class S>
+__device__ void seed_filter(S& st, const FindArgs& a, int k) {
+    Scalars& sc = *st.s;
+    const Params& p = a.p;
+    const int nc = sc.n_cand;
+    const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
+    const float dz2 = p.z[k + 2] - p.z[k];
+    const float dz1 = p.z[k + 1] - p.z[k];
+    const float zk = p.z[k];
+    const float fk = (float)k;
+    const float fn0 = (float)(sc.cb[k + 1] - sc.cb[k]);
+    const float fn1 = (float)(sc.cb[k + 2] - sc.cb[k + 1]);
+    const float fn2 = (float)(sc.cb[k + 3] - sc.cb[k + 2]);
+    const float* W = a.seed_net;
+    const bool on = W != nullptr;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int o = lane & (kSeedH - 1);
+    const int hb = lane & kSeedH;  // first lane of this half-wave
+    constexpr int kGroups = kT / kSeedH;
+    static_assert(kWave == 2 * kSeedH, "two candidates per wave");
+    for (int c0 = 0; c0 < nc; c0 += kGroups) {
+        const int c = c0 + (int)threadIdx.x / kSeedH;
+        const bool valid = c < nc;
+        const int cc = valid ? c : nc - 1;  // idle half-waves still take part in the broadcasts
+        const int i0 = st.cp(cc, 0), i1 = st.cp(cc, 1), i2 = st.cp(cc, 2);
+        const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
+        const float tx = (st.X(s2, i2) - x0) / dz2;
+        const float ty = (st.Y(s2, i2) - y0) / dz2;
+        const float ex = x0 + tx * dz1;
+        const float ey = y0 + ty * dz1;
+        const float dx = st.X(s1, i1) - ex;
+        const float dy = st.Y(s1, i1) - ey;
+        const float t2 = tx * tx + ty * ty;
+        const float rt = x0 * tx + y0 * ty;
+        const float cr = x0 * ty - y0 * tx;
+        const float r2 = x0 * x0 + y0 * y0;
+        float zc = zk - rt / t2;
+        zc = zc < -kSeedZLim ? -kSeedZLim : (zc > kSeedZLim ? kSeedZLim : zc);
+        const float f[kSeedIn] = {dx * dx + dy * dy, cr * cr / t2, zc, r2, t2, rt * rt / (r2 * t2), fk, fn0, fn1, fn2};
+        if (a.seed_feat && valid && o == 0) {
+            const unsigned long long slot = atomicAdd(a.seed_count, 1ull);
+            if (slot < (unsigned long long)a.seed_cap) {
+                for (int i = 0; i < kSeedIn; ++i) a.seed_feat[slot * kSeedIn + i] = f[i];
+                a.seed_hits[slot * 3] = (int32_t)st.ID(s0, i0);
+                a.seed_hits[slot * 3 + 1] = (int32_t)st.ID(s1, i1);
+                a.seed_hits[slot * 3 + 2] = (int32_t)st.ID(s2, i2);
+            }
+        }
+        if (on) {
+            // weights re-read (L1 / scalar cache) per candidate rather than
+            // held in registers across the loop, which would cost the rest of
+            // the finder its occupancy
+            const float* Wc = W;
+            asm volatile("" : "+s"(Wc));
+            W = Wc;
+            float h = W[kSeedB1 + o];
+            for (int i = 0; i < kSeedIn; ++i) {
+                const float xs = (f[i] - W[kSeedNorm + i]) / W[kSeedNorm + kSeedIn + i];
+                h = h + W[kSeedW1T + i * kSeedH + o] * xs;
+            }
+            const float h1 = h > 0.0f ? h : 0.0f;
+            h = W[kSeedB2 + o];
+            for (int i = 0; i < kSeedH; ++i) h = h + W[kSeedW2T + i * kSeedH + o] * __shfl(h1, hb + i);
+            const float h2 = h > 0.0f ? h : 0.0f;
+            float z = W[kSeedB3];
+            for (int i = 0; i < kSeedH; ++i) z = z + W[kSeedW3 + i] * __shfl(h2, hb + i);
+            if (valid && o == 0 && z > W[kSeedThr]) st.calive(c) = 0;
+        }
+    }
+    __syncthreads();
+}
+
 // Whole event.  Returns false when a capacity was too small (LDS tile: redo on
 // the large path; large path: overflow); on true the candidates are final.
-template <int kT, class S>
+template <int kT, bool kSeed, class S>
 __device__ bool find_event(S& st, const FindArgs& a, int e) {
     Scalars& sc = *st.s;
     if (threadIdx.x == 0) {
@@ -1043,6 +1121,7 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
             if (!enumerate_seeds<kT>(st, a, k)) return false;
             PHASE(2);
             if (sc.n_cand > 0) {
+                if constexpr (kSeed) seed_filter<kT>(st, a, k);
                 claim_seeds<kT>(st, a, k);
                 PHASE(3);
                 if (!create_tracks<kT>(st, a, k)) return false;
@@ -1063,7 +1142,9 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
     set_event_flag(a.status, e, flag, 1);
 }
 
-template <int kT, int kP, int kTr, int kC>
+// kSeed: the variant with the seed filter / emission (separate code, so that
+// the plain finder keeps its register allocation and occupancy).
+template <int kT, int kP, int kTr, int kC, bool kSeed>
 __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) {
     __shared__ Tile<kP, kTr, kC> tile;
     __shared__ Scalars sc;
@@ -1089,7 +1170,7 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) 
         bool ok = false;
         if (!big) {
             st.slot0 = a.clu_off[e * kPlanes];
-            ok = find_event<kT>(st, a, e);
+            ok = find_event<kT, kSeed>(st, a, e);
         }
         if (!ok && threadIdx.x == 0) {
             const int i = atomicAdd(a.w.counters + 2, 1);
@@ -1099,7 +1180,7 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) 
     }
 }
 
-template <int kT>
+template <int kT, bool kSeed>
 __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     __shared__ Scalars sc;
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
@@ -1140,7 +1221,7 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
         st.slot0 = c0;
         st.cap_t = (int)((c1 - c0) / 3 + 1);
         __syncthreads();
-        const bool ok = find_event<kT>(st, a, e);
+        const bool ok = find_event<kT, kSeed>(st, a, e);
         if (!ok && threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
         __syncthreads();
     }
@@ -1198,18 +1279,23 @@ __global__ __launch_bounds__(256) void k_accept(FindArgs a) {
     }
 }
 
+bool seed_variant(const FindArgs& a) { return a.seed_net != nullptr || a.seed_feat != nullptr; }
+
 template <int kT, int kP, int kTr, int kC>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC>), dim3(grid), dim3(kT), 0, s, a);
+    if (seed_variant(a))
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, true>), dim3(grid), dim3(kT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, false>), dim3(grid), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
 template <int kT, int kP, int kTr, int kC>
-int occ_lds() {
+int occ_lds(bool seed) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC>, kT, 0) != hipSuccess)
-        return 1;
-    return n;
+    const hipError_t e = seed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, true>, kT, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, false>, kT, 0);
+    return e == hipSuccess ? n : 1;
 }
 
 }  // namespace
@@ -1233,9 +1319,9 @@ hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, h
 #undef VELO_CASE
 }
 
-int find_blocks_per_cu(int threads, int tile) {
+int find_blocks_per_cu(int threads, int tile, bool seed) {
 #define VELO_CASE(T, L, P, TR, C) \
-    case T * 4 + L: return occ_lds<T, P, TR, C>();
+    case T * 4 + L: return occ_lds<T, P, TR, C>(seed);
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
@@ -1247,7 +1333,10 @@ int find_blocks_per_cu(int threads, int tile) {
 }
 
 hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_find_large<256>, dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
+    if (seed_variant(a))
+        hipLaunchKernelGGL((k_find_large<256, true>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_find_large<256, false>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -40,6 +40,11 @@ struct FindArgs {
     const float* mlp_master;  // learned mode: FP32 master weights (device)
     const float* mlp_norm;    // 20 floats
     int64_t clu_limit;        // events whose clusters reach beyond this are not processed
+    const float* seed_net;    // seed filter network, kSeedFloats (null: no seed filter)
+    float* seed_feat;         // seed emission for training: [seed_cap][10] features (null: off)
+    int32_t* seed_hits;       // [seed_cap][3] global cluster indices
+    int64_t seed_cap;
+    unsigned long long* seed_count;  // candidates seen (may exceed seed_cap)
 };
 
 struct OutArgs {

@@ -39,6 +39,6 @@ hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const u
                            float* loss, hipStream_t s);
 hipError_t launch_adam(MlpState& m, float lr, hipStream_t s);
 
-int find_blocks_per_cu(int threads, int tile);
+int find_blocks_per_cu(int threads, int tile, bool seed);
 
 }  // namespace velo

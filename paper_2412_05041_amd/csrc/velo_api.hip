@@ -57,6 +57,13 @@ struct velo_ctx {
     GraphKey key;
     uint64_t version = 1;  // bumped by anything that changes captured parameters
     MlpState mlp;
+    // seed-level filter (kSeedFloats on the device) and its training emission
+    float* d_seed = nullptr;
+    int seed_on = 0;
+    float* seed_feat = nullptr;
+    int32_t* seed_hits = nullptr;
+    int64_t seed_cap = 0;
+    unsigned long long* seed_count = nullptr;
     // stage timing (eager pipeline)
     int timing = 0;
     hipEvent_t ev[VELO_N_STAGES + 1] = {};
@@ -175,7 +182,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
 }
 
 int grid_for(velo_ctx* c, int n_events) {
-    const int per_cu = find_blocks_per_cu(c->threads, c->tile);
+    const int per_cu = find_blocks_per_cu(c->threads, c->tile, c->seed_on || c->seed_feat);
     const int g = std::max(1, c->n_cu * std::min(std::max(per_cu, 1), kMaxLdsBlocksPerCu));
     return std::max(1, std::min(n_events, g));
 }
@@ -204,6 +211,11 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     fa.mlp_master = c->mlp.d_master;
     fa.mlp_norm = c->mlp.d_norm;
     fa.clu_limit = clu_limit;
+    fa.seed_net = c->seed_on ? c->d_seed : nullptr;
+    fa.seed_feat = c->seed_feat;
+    fa.seed_hits = c->seed_hits;
+    fa.seed_cap = c->seed_cap;
+    fa.seed_count = c->seed_count;
     HIP_OK(launch_find_lds(fa, c->threads, c->tile, grid_for(c, E), s));
     if (int rc = mark(c, 4, s, timed)) return rc;
     HIP_OK(launch_find_large(fa, s));
@@ -284,6 +296,11 @@ int velo_create(const velo_geometry* g, const velo_cuts* cu, int device, velo_ct
     if (e != hipSuccess) { delete c; return fail(VELO_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
     rc = mlp_init(c->mlp);
     if (rc) { delete c; return fail(VELO_ERR_DEVICE, "MLP state allocation failed"); }
+    if (hipMalloc(&c->d_seed, sizeof(float) * kSeedFloats) != hipSuccess) {
+        mlp_free(c->mlp);
+        delete c;
+        return fail(VELO_ERR_DEVICE, "seed filter allocation failed");
+    }
     *out = c;
     return VELO_OK;
 }
@@ -298,6 +315,7 @@ void velo_destroy(velo_ctx* c) {
     for (int i = 0; i <= VELO_N_STAGES; ++i)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     mlp_free(c->mlp);
+    if (c->d_seed) (void)hipFree(c->d_seed);
     delete c;
 }
 
@@ -589,6 +607,7 @@ int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* c
             fa.p.mode = 0;
             fa.w = c->w;
             fa.clu_limit = c->w.cap_clusters;
+            fa.seed_net = c->seed_on ? c->d_seed : nullptr;
             float tot = 0.0f;
             for (int r = 0; r <= reps; ++r) {
                 HIP_OK(launch_reset(c->w, E, nullptr, s));
@@ -647,6 +666,55 @@ int velo_status_read(velo_ctx* c, const int32_t* d_status, int32_t* h_status, in
 
 // ---------------------------------------------------------------- learned filter
 extern "C" {
+
+int velo_seed_filter_set(velo_ctx* c, const float* h_weights, const float* h_norm, float threshold) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (!h_weights) {
+        c->seed_on = 0;
+        c->version++;
+        return VELO_OK;
+    }
+    if (!h_norm) return fail(VELO_ERR_ARG, "null normalisation");
+    for (int i = 0; i < kSeedIn; ++i)
+        if (!(h_norm[kSeedIn + i] != 0.0f)) return fail(VELO_ERR_ARG, "normalisation sd must be non-zero");
+    // host layout of the track network: W1 [unit][input], b1, W2 [unit][input], b2, w3, b3
+    std::vector<float> d(kSeedFloats);
+    for (int o = 0; o < kSeedH; ++o) {
+        for (int i = 0; i < kSeedIn; ++i) d[kSeedW1T + i * kSeedH + o] = h_weights[o * kSeedIn + i];
+        d[kSeedB1 + o] = h_weights[kSeedIn * kSeedH + o];
+        for (int i = 0; i < kSeedH; ++i)
+            d[kSeedW2T + i * kSeedH + o] = h_weights[kSeedIn * kSeedH + kSeedH + o * kSeedH + i];
+        d[kSeedB2 + o] = h_weights[kSeedIn * kSeedH + kSeedH + kSeedH * kSeedH + o];
+        d[kSeedW3 + o] = h_weights[kSeedIn * kSeedH + 2 * kSeedH + kSeedH * kSeedH + o];
+    }
+    d[kSeedB3] = h_weights[kSeedIn * kSeedH + 3 * kSeedH + kSeedH * kSeedH];
+    for (int i = 0; i < 2 * kSeedIn; ++i) d[kSeedNorm + i] = h_norm[i];
+    d[kSeedThr] = threshold;
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(hipMemcpy(c->d_seed, d.data(), sizeof(float) * kSeedFloats, hipMemcpyHostToDevice));
+    c->seed_on = 1;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_seed_emit(velo_ctx* c, float* d_feat, int32_t* d_hits, int64_t cap, unsigned long long* d_count) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (!d_feat && !d_hits && !d_count) {
+        c->seed_feat = nullptr;
+        c->seed_hits = nullptr;
+        c->seed_cap = 0;
+        c->seed_count = nullptr;
+        c->version++;
+        return VELO_OK;
+    }
+    if (!d_feat || !d_hits || !d_count || cap < 0) return fail(VELO_ERR_ARG, "seed emission needs all three buffers");
+    c->seed_feat = d_feat;
+    c->seed_hits = d_hits;
+    c->seed_cap = cap;
+    c->seed_count = d_count;
+    c->version++;
+    return VELO_OK;
+}
 
 int velo_mlp_set_weights(velo_ctx* c, const float* h_master, const float* h_norm) {
     if (!c || !h_master || !h_norm) return fail(VELO_ERR_ARG, "null argument");

@@ -55,6 +55,8 @@ _SIGS = {
     "velo_autotune": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                       C.c_void_p],
     "velo_mlp_set_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "velo_seed_filter_set": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float],
+    "velo_seed_emit": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "velo_mlp_get_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_features": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
     "velo_mlp_forward": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -318,6 +320,35 @@ class Velo:
         h = (C.c_int32 * n)()
         _check(lib().velo_status_read(self.h, _ptr(status), h, n, _stream()))
         return np.frombuffer(h, np.int32).copy()
+
+    # ---------------------------------------------------------------- seed-level filter
+    def seed_filter_set(self, weights, norm=None, threshold=0.0):
+        """Seed-level filter: weights[1441] (track-network order, used as given
+        in FP32), norm[20], a logit threshold; weights=None switches it off."""
+        if weights is None:
+            _check(lib().velo_seed_filter_set(self.h, None, None, C.c_float(0.0)))
+            return
+        w = np.ascontiguousarray(weights, np.float32)
+        n = np.ascontiguousarray(norm, np.float32)
+        if w.size != N_PARAM or n.size != 20:
+            raise ValueError("seed filter needs 1441 weights and 20 normalisation values")
+        _check(lib().velo_seed_filter_set(self.h, w.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p),
+                                          C.c_float(threshold)))
+
+    def seed_emit(self, cap):
+        """Switch on seed emission into fresh device buffers of `cap` rows
+        (cap=0: off).  Returns dict(feat [cap][10], hits [cap][3], count [1]);
+        the caller reads count[0] (all candidates seen) after the finder ran."""
+        if cap <= 0:
+            _check(lib().velo_seed_emit(self.h, None, None, 0, None))
+            self._seed_buf = None
+            return None
+        buf = dict(feat=torch.empty((cap, 10), dtype=torch.float32, device=self.device),
+                   hits=torch.empty((cap, 3), dtype=torch.int32, device=self.device),
+                   count=torch.zeros(1, dtype=torch.int64, device=self.device))
+        self._seed_buf = buf  # keeps the buffers alive while emission is on
+        _check(lib().velo_seed_emit(self.h, _ptr(buf["feat"]), _ptr(buf["hits"]), cap, _ptr(buf["count"])))
+        return buf
 
     # ---------------------------------------------------------------- learned filter
     def mlp_set_weights(self, master, norm):
