@@ -11,7 +11,7 @@ Prints ONE JSON line: events/s, the dominant kernel's HBM roofline fraction
 (algorithmic bytes / its HIP-event-timed duration), efficiency / ghost rate of
 the output, and the oracle timed on the host cores over a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode plain|learned]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode plain|learned] [--seed-filter]
 """
 import argparse
 import json
@@ -30,14 +30,14 @@ def _oracle_chunk(args):
     """CPU baseline worker: the oracle (cluster + find + FP64 fit) on an event slice."""
     import numpy as np  # noqa: F401
     import oracle
-    pix_off, pix_id, plane_z, cuts = args
+    pix_off, pix_id, plane_z, cuts, seed = args
     c = oracle.cluster(pix_off, pix_id)
-    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], plane_z, cuts)
+    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], plane_z, cuts, seed=seed)
     oracle.fit(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], plane_z, cuts["sigma"])
     return int(pix_off.size - 1) // 26
 
 
-def cpu_baseline(batch, cuts, passes, min_wall):
+def cpu_baseline(batch, cuts, passes, min_wall, seed=None):
     import multiprocessing as mp
 
     import oracle
@@ -47,7 +47,7 @@ def cpu_baseline(batch, cuts, passes, min_wall):
     step = max(1, batch.n_events // (cores * 4))
     for e0 in range(0, batch.n_events, step):
         s = batch.event_slice(e0, min(batch.n_events, e0 + step))
-        chunks.append((s.pix_off, s.pix_id, batch.plane_z, cuts))
+        chunks.append((s.pix_off, s.pix_id, batch.plane_z, cuts, seed))
     ctx = mp.get_context("fork")  # no GPU has been touched yet in this process
     with ctx.Pool(cores) as pool:
         pool.map(_oracle_chunk, chunks[:cores])  # warm the workers
@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["plain", "learned"], default="plain")
+    ap.add_argument("--seed-filter", action="store_true",
+                    help="seed-level learned filter with the committed network (configs/seed_default.npz)")
     ap.add_argument("--path", choices=["fused", "three-call"], default="fused",
                     help="fused: velo_pipeline (one replayed HIP graph); three-call: velo_cluster, "
                          "velo_find_tracks, velo_fit launched eagerly")
@@ -135,9 +137,15 @@ def main():
     E = batch.n_events
     log(f"generated {E} {w.name} events, {batch.n_pix} pixels")
 
+    seed_net = None
+    if args.seed_filter:
+        import numpy as np
+        d = np.load(os.path.join(cfg, "seed_default.npz"), allow_pickle=False)
+        seed_net = (d["weights"].astype(np.float32), d["norm"].astype(np.float32), float(d["threshold"]))
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, cuts, args.cpu_passes, args.cpu_seconds)
+        cpu = cpu_baseline(batch, cuts, args.cpu_passes, args.cpu_seconds, seed=seed_net)
         log(f"cpu baseline: {cpu['value']:.0f} events/s on {cpu['cores']} cores")
 
     import torch
@@ -151,6 +159,8 @@ def main():
     v = velo.Velo(batch.plane_z, cuts, device=0)
     if args.mode == "learned":
         v.mlp_set_weights(master, norm)
+    if seed_net is not None:
+        v.seed_filter_set(*seed_net)
     v.reserve(E, batch.n_pix, batch.n_pix)
     off, ids = velo.to_device(batch)
     tune_ms = None
@@ -285,6 +295,7 @@ def main():
             "clusters_per_event": n_clu / E,
             "tracks_per_event": T / E,
             "mode": args.mode,
+            "seed_filter": bool(args.seed_filter),
             "path": args.path,
             "kalman_ms": args.kalman,
             "raw_banks": bool(args.raw),

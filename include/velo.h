@@ -116,9 +116,13 @@ int velo_set_cuts(velo_ctx* ctx, const velo_cuts* cuts);
  * flag VELO_EV_BAD_INPUT instead of clustering malformed segments. */
 int velo_set_validate(velo_ctx* ctx, int32_t on);
 
-/* The only call that allocates device memory (the internal workspace).  Must be
- * made before any other enqueue and before stream capture; may be repeated to
- * grow.  max_clusters bounds the clusters of a batch (<= max_pixels). */
+/* The only call that allocates the internal workspace (velo_create allocates
+ * the small network states).  Must be made before any other enqueue and before
+ * stream capture; may be repeated to grow.  max_clusters bounds the clusters of
+ * a batch (<= max_pixels).  The large-event finder's candidate pool follows
+ * the mean event size (max_clusters / max_events), so a repeated call for fewer,
+ * larger events lays the workspace out again even when the counts fit (every
+ * earlier capacity is kept). */
 int velo_reserve(velo_ctx* ctx, int32_t max_events, int64_t max_pixels, int64_t max_clusters);
 
 /* Pixel clustering (connected components, 8-neighbourhood).
@@ -263,7 +267,8 @@ int velo_mlp_set_state(velo_ctx* ctx, const float* h_master, const float* h_m, c
  * approach to the axis (clipped to +-2000 mm), h0's squared radius, the squared
  * slope, the squared cosine between h0's radial direction and the slope, the
  * plane k and the cluster counts of planes k, k+1, k+2.  The network runs in
- * FP32 (bias first, inputs ascending, ReLU; no BF16 rounding), and a candidate
+ * FP32 (features standardised as (f - mean) * r, r = 1 / sd rounded to FP32;
+ * each unit from its bias, inputs ascending, ReLU; no BF16 rounding); a candidate
  * whose logit exceeds `threshold` is dropped before the claiming, which changes
  * the tracks found.  h_weights: 1441 floats in the track network's order
  * (pass BF16-rounded values to reproduce a BF16-trained network); h_norm: 10

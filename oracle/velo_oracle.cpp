@@ -375,12 +375,16 @@ void seed_features(const EventIn& ev, int k, int h0, int h1, int h2, float* f) {
     f[9] = float(ev.base[k + 3] - ev.base[k + 2]);
 }
 
-// The seed network in FP32: standardise, then each unit starts from its bias
-// and adds weight x input for inputs in ascending order; ReLU between layers.
+// The seed network in FP32: standardise as (f - mean) * r with r = 1 / sd
+// rounded to FP32, then each unit starts from its bias and adds weight x input
+// for inputs in ascending order; ReLU between layers.
 float seed_logit(const vo_seed_net& sn, const float* f) {
     const float* w = sn.w;
     float xs[kIn], h1[kH], h2[kH];
-    for (int i = 0; i < kIn; ++i) xs[i] = (f[i] - sn.norm[i]) / sn.norm[kIn + i];
+    for (int i = 0; i < kIn; ++i) {
+        const float r = 1.0f / sn.norm[kIn + i];
+        xs[i] = (f[i] - sn.norm[i]) * r;
+    }
     for (int o = 0; o < kH; ++o) {
         float a = w[oB1 + o];
         for (int i = 0; i < kIn; ++i) a = a + w[oW1 + o * kIn + i] * xs[i];

@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 // Seed-level filter network (10 -> 32 -> 32 -> 1) as the finder reads it: the
 // first two weight matrices transposed ([input][unit], so the 32 lanes of a
 // half-wave read one row), biases, output weights, the feature normalisation
-// (10 means, 10 standard deviations) and the rejection threshold.
+// (10 means, 10 reciprocal standard deviations) and the rejection threshold.
 constexpr int kSeedIn = 10, kSeedH = 32;
 constexpr int kSeedW1T = 0, kSeedB1 = kSeedW1T + kSeedIn * kSeedH, kSeedW2T = kSeedB1 + kSeedH,
               kSeedB2 = kSeedW2T + kSeedH * kSeedH, kSeedW3 = kSeedB2 + kSeedH, kSeedB3 = kSeedW3 + kSeedH,

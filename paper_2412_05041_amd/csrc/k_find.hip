@@ -177,6 +177,8 @@ struct GlobalStore {
     int64_t pool0;   // first seed-pool entry of this workgroup
     int cap_t;
     int seed_k = 0;  // plane of h0 during seeding
+    const float* seedw = nullptr;  // seed network in LDS, rows [unit][input] (seed variant)
+    float* seedh = nullptr;        // per-thread first-layer activations in LDS, [unit][thread]
     __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
     __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
     __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
@@ -1011,78 +1013,132 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
 }
 
 // Seed-level learned filter and training emission, between enumeration and
-// claiming.  A half-wave (32 lanes) takes one candidate: every lane forms its
-// ten features, lane o evaluates hidden unit o of both layers with the inputs
-// broadcast across the half-wave, and every lane sums the output unit.  A
-// candidate whose logit exceeds the threshold dies.  FP32 in a fixed order:
-// each unit starts from its bias and adds weight x input, inputs ascending.
+// claiming.  Features of candidate c (the ten values of the seed filter, FP32,
+// each in one fixed order).
+template <class S>
+__device__ __forceinline__ void seed_features(S& st, const Params& p, int k, int c, const float* fn, float* f,
+                                              int* i0, int* i1, int* i2) {
+    const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
+    *i0 = st.cp(c, 0);
+    *i1 = st.cp(c, 1);
+    *i2 = st.cp(c, 2);
+    const float dz2 = p.z[k + 2] - p.z[k];
+    const float dz1 = p.z[k + 1] - p.z[k];
+    const float x0 = st.X(s0, *i0), y0 = st.Y(s0, *i0);
+    const float tx = (st.X(s2, *i2) - x0) / dz2;
+    const float ty = (st.Y(s2, *i2) - y0) / dz2;
+    const float ex = x0 + tx * dz1;
+    const float ey = y0 + ty * dz1;
+    const float dx = st.X(s1, *i1) - ex;
+    const float dy = st.Y(s1, *i1) - ey;
+    const float t2 = tx * tx + ty * ty;
+    const float rt = x0 * tx + y0 * ty;
+    const float cr = x0 * ty - y0 * tx;
+    const float r2 = x0 * x0 + y0 * y0;
+    float zc = p.z[k] - rt / t2;
+    zc = zc < -kSeedZLim ? -kSeedZLim : (zc > kSeedZLim ? kSeedZLim : zc);
+    f[0] = dx * dx + dy * dy;
+    f[1] = cr * cr / t2;
+    f[2] = zc;
+    f[3] = r2;
+    f[4] = t2;
+    f[5] = rt * rt / (r2 * t2);
+    f[6] = fn[0];
+    f[7] = fn[1];
+    f[8] = fn[2];
+    f[9] = fn[3];
+}
+
+// The network evaluates in FP32 in one fixed order: features standardised as
+// (f - mean) * (1 / sd), each unit starts from its bias and adds weight x input
+// for inputs in ascending order, ReLU between layers.  Two layouts of the same
+// arithmetic: a half-wave per candidate (lane o holds hidden unit o, inputs
+// broadcast across the half-wave), and -- in the large-event finder, whose
+// crowded plane steps bring thousands of candidates -- one candidate per lane
+// with the weights read from an LDS copy as uniform operands.  A candidate
+// whose logit exceeds the threshold dies.
 template <int kT, class S>
 __device__ void seed_filter(S& st, const FindArgs& a, int k) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
     const int nc = sc.n_cand;
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
-    const float dz2 = p.z[k + 2] - p.z[k];
-    const float dz1 = p.z[k + 1] - p.z[k];
-    const float zk = p.z[k];
-    const float fk = (float)k;
-    const float fn0 = (float)(sc.cb[k + 1] - sc.cb[k]);
-    const float fn1 = (float)(sc.cb[k + 2] - sc.cb[k + 1]);
-    const float fn2 = (float)(sc.cb[k + 3] - sc.cb[k + 2]);
+    const float fn[4] = {(float)k, (float)(sc.cb[k + 1] - sc.cb[k]), (float)(sc.cb[k + 2] - sc.cb[k + 1]),
+                         (float)(sc.cb[k + 3] - sc.cb[k + 2])};
     const float* W = a.seed_net;
     const bool on = W != nullptr;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int o = lane & (kSeedH - 1);
-    const int hb = lane & kSeedH;  // first lane of this half-wave
-    constexpr int kGroups = kT / kSeedH;
-    static_assert(kWave == 2 * kSeedH, "two candidates per wave");
-    for (int c0 = 0; c0 < nc; c0 += kGroups) {
-        const int c = c0 + (int)threadIdx.x / kSeedH;
-        const bool valid = c < nc;
-        const int cc = valid ? c : nc - 1;  // idle half-waves still take part in the broadcasts
-        const int i0 = st.cp(cc, 0), i1 = st.cp(cc, 1), i2 = st.cp(cc, 2);
-        const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
-        const float tx = (st.X(s2, i2) - x0) / dz2;
-        const float ty = (st.Y(s2, i2) - y0) / dz2;
-        const float ex = x0 + tx * dz1;
-        const float ey = y0 + ty * dz1;
-        const float dx = st.X(s1, i1) - ex;
-        const float dy = st.Y(s1, i1) - ey;
-        const float t2 = tx * tx + ty * ty;
-        const float rt = x0 * tx + y0 * ty;
-        const float cr = x0 * ty - y0 * tx;
-        const float r2 = x0 * x0 + y0 * y0;
-        float zc = zk - rt / t2;
-        zc = zc < -kSeedZLim ? -kSeedZLim : (zc > kSeedZLim ? kSeedZLim : zc);
-        const float f[kSeedIn] = {dx * dx + dy * dy, cr * cr / t2, zc, r2, t2, rt * rt / (r2 * t2), fk, fn0, fn1, fn2};
-        if (a.seed_feat && valid && o == 0) {
-            const unsigned long long slot = atomicAdd(a.seed_count, 1ull);
-            if (slot < (unsigned long long)a.seed_cap) {
-                for (int i = 0; i < kSeedIn; ++i) a.seed_feat[slot * kSeedIn + i] = f[i];
-                a.seed_hits[slot * 3] = (int32_t)st.ID(s0, i0);
-                a.seed_hits[slot * 3 + 1] = (int32_t)st.ID(s1, i1);
-                a.seed_hits[slot * 3 + 2] = (int32_t)st.ID(s2, i2);
+    auto emit = [&](const float* f, int i0, int i1, int i2) {
+        const unsigned long long slot = atomicAdd(a.seed_count, 1ull);
+        if (slot < (unsigned long long)a.seed_cap) {
+            for (int i = 0; i < kSeedIn; ++i) a.seed_feat[slot * kSeedIn + i] = f[i];
+            a.seed_hits[slot * 3] = (int32_t)st.ID(s0, i0);
+            a.seed_hits[slot * 3 + 1] = (int32_t)st.ID(s1, i1);
+            a.seed_hits[slot * 3 + 2] = (int32_t)st.ID(s2, i2);
+        }
+    };
+    bool per_lane = false;
+    if constexpr (S::kLarge) per_lane = on && nc >= kT / 4;
+    if (per_lane) {
+        if constexpr (S::kLarge) {
+            const float* sw = st.seedw;
+            for (int c = threadIdx.x; c < nc; c += kT) {
+                float f[kSeedIn];
+                int i0, i1, i2;
+                seed_features(st, p, k, c, fn, f, &i0, &i1, &i2);
+                if (a.seed_feat) emit(f, i0, i1, i2);
+                float xs[kSeedIn], h1[kSeedH];
+                for (int i = 0; i < kSeedIn; ++i) xs[i] = (f[i] - sw[kSeedNorm + i]) * sw[kSeedNorm + kSeedIn + i];
+                // first layer through LDS (a rolled loop keeps the registers
+                // for the rest of the finder), read back for the second
+                float* hs = st.seedh;
+#pragma unroll 1
+                for (int o = 0; o < kSeedH; ++o) {
+                    float h = sw[kSeedB1 + o];
+                    for (int i = 0; i < kSeedIn; ++i) h = h + sw[kSeedW1T + o * kSeedIn + i] * xs[i];
+                    hs[o * kT + threadIdx.x] = h > 0.0f ? h : 0.0f;
+                }
+                for (int o = 0; o < kSeedH; ++o) h1[o] = hs[o * kT + threadIdx.x];
+                float z = sw[kSeedB3];
+#pragma unroll 1
+                for (int o = 0; o < kSeedH; ++o) {
+                    float h = sw[kSeedB2 + o];
+                    for (int i = 0; i < kSeedH; ++i) h = h + sw[kSeedW2T + o * kSeedH + i] * h1[i];
+                    z = z + sw[kSeedW3 + o] * (h > 0.0f ? h : 0.0f);
+                }
+                if (z > sw[kSeedThr]) st.calive(c) = 0;
             }
         }
-        if (on) {
+    } else {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int o = lane & (kSeedH - 1);
+        const int hb = lane & kSeedH;  // first lane of this half-wave
+        constexpr int kGroups = kT / kSeedH;
+        static_assert(kWave == 2 * kSeedH, "two candidates per wave");
+        for (int c0 = 0; c0 < nc; c0 += kGroups) {
+            const int c = c0 + (int)threadIdx.x / kSeedH;
+            const bool valid = c < nc;
+            // idle half-waves take a valid candidate and still join the broadcasts
+            float f[kSeedIn];
+            int i0, i1, i2;
+            seed_features(st, p, k, valid ? c : nc - 1, fn, f, &i0, &i1, &i2);
+            if (a.seed_feat && valid && o == 0) emit(f, i0, i1, i2);
+            if (!on) continue;
             // weights re-read (L1 / scalar cache) per candidate rather than
-            // held in registers across the loop, which would cost the rest of
-            // the finder its occupancy
+            // held in registers across the loop
             const float* Wc = W;
             asm volatile("" : "+s"(Wc));
-            W = Wc;
-            float h = W[kSeedB1 + o];
+            float h = Wc[kSeedB1 + o];
             for (int i = 0; i < kSeedIn; ++i) {
-                const float xs = (f[i] - W[kSeedNorm + i]) / W[kSeedNorm + kSeedIn + i];
-                h = h + W[kSeedW1T + i * kSeedH + o] * xs;
+                const float xs = (f[i] - Wc[kSeedNorm + i]) * Wc[kSeedNorm + kSeedIn + i];
+                h = h + Wc[kSeedW1T + i * kSeedH + o] * xs;
             }
             const float h1 = h > 0.0f ? h : 0.0f;
-            h = W[kSeedB2 + o];
-            for (int i = 0; i < kSeedH; ++i) h = h + W[kSeedW2T + i * kSeedH + o] * __shfl(h1, hb + i);
+            h = Wc[kSeedB2 + o];
+            for (int i = 0; i < kSeedH; ++i) h = h + Wc[kSeedW2T + i * kSeedH + o] * __shfl(h1, hb + i);
             const float h2 = h > 0.0f ? h : 0.0f;
-            float z = W[kSeedB3];
-            for (int i = 0; i < kSeedH; ++i) z = z + W[kSeedW3 + i] * __shfl(h2, hb + i);
-            if (valid && o == 0 && z > W[kSeedThr]) st.calive(c) = 0;
+            float z = Wc[kSeedB3];
+            for (int i = 0; i < kSeedH; ++i) z = z + Wc[kSeedW3 + i] * __shfl(h2, hb + i);
+            if (valid && o == 0 && z > Wc[kSeedThr]) st.calive(c) = 0;
         }
     }
     __syncthreads();
@@ -1184,8 +1240,29 @@ template <int kT, bool kSeed>
 __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     __shared__ Scalars sc;
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
+    __shared__ __align__(16) float seedw[kSeed ? kSeedFloats : 1];
+    __shared__ float seedh[kSeed ? kSeedH * kT : 1];
     GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
     st.luts = luts;
+    st.seedh = seedh;
+    if constexpr (kSeed) {
+        // the seed network with its weight matrices back in [unit][input] rows
+        if (a.seed_net) {
+            for (int i = threadIdx.x; i < kSeedFloats; i += kT) {
+                float v = a.seed_net[i];
+                if (i < kSeedB1) {
+                    const int o = i / kSeedIn, j = i % kSeedIn;
+                    v = a.seed_net[kSeedW1T + j * kSeedH + o];
+                } else if (i >= kSeedW2T && i < kSeedB2) {
+                    const int o = (i - kSeedW2T) / kSeedH, j = (i - kSeedW2T) % kSeedH;
+                    v = a.seed_net[kSeedW2T + j * kSeedH + o];
+                }
+                seedw[i] = v;
+            }
+            st.seedw = seedw;
+        }
+        __syncthreads();
+    }
     st.cell = a.w.g_cell + (int64_t)blockIdx.x * kCellWords;
     const int n_large = a.w.counters[2];
     while (true) {

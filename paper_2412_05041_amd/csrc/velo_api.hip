@@ -115,7 +115,14 @@ T* carve(char*& cur, int64_t n) {
     return p;
 }
 
-size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
+// Seed-candidate pool entries per large-event workgroup for a reservation of
+// E events and C clusters: from the mean event (16 entries per cluster: noise-
+// dominated planes give ~2 candidates per hit pair passing the pair cuts).
+int64_t pool_entries(int32_t E, int64_t C) {
+    return std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 23, 16 * (C / std::max(E, 1))));
+}
+
+size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, int64_t min_pool) {
     char* cur = base;
     const int64_t PX = std::max(P, C);
     w.sx = carve<float>(cur, C);
@@ -157,11 +164,11 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu) {
     w.g_gy = carve<float>(cur, C);
     w.g_gpos = carve<int32_t>(cur, C);
     // global-memory finder: each workgroup owns a seed-candidate pool for one
-    // plane step of its current event, sized from the mean event (16 entries
-    // per cluster: noise-dominated planes give ~2 candidates per hit pair
-    // passing the pair cuts); as many workgroups as a pool budget of 8 entries
-    // per cluster allows (at most 2 per CU, at least 1)
-    w.pool_cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 23, 16 * (C / std::max(E, 1))));
+    // plane step of its current event (pool_entries, or min_pool when larger:
+    // a reservation kept for a batch of fewer, larger events); as many
+    // workgroups as a pool budget of 8 entries per cluster allows (at most 2
+    // per CU, at least 1)
+    w.pool_cap = std::max(pool_entries(E, C), min_pool);
     const int64_t budget = std::max<int64_t>(1 << 20, std::min<int64_t>(int64_t(1) << 29, 8 * C));
     w.n_large_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2 * std::max(n_cu, 1), budget / w.pool_cap));
     w.g_cell = carve<int32_t>(cur, kCellWords * w.n_large_blocks);
@@ -354,9 +361,20 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
     if (max_events < 0 || max_pixels < 0 || max_clusters < 0 || max_clusters > max_pixels + 1)
         return fail(VELO_ERR_ARG, "bad reserve sizes");
     if (max_pixels >= (int64_t)1 << 31) return fail(VELO_ERR_UNSUPPORTED, "more than 2^31 pixels per batch");
+    // the large-event pool follows the mean event size, so a workspace that
+    // covers the counts but was laid out for smaller events is laid out again
+    const int64_t want_pool = pool_entries(std::max(max_events, 1), std::max<int64_t>(max_clusters, 1));
     if (c->ws && max_events <= c->w.cap_events && max_pixels <= c->w.cap_pixels &&
-        max_clusters <= c->w.cap_clusters)
+        max_clusters <= c->w.cap_clusters && want_pool <= c->w.pool_cap)
         return VELO_OK;
+    int32_t E = std::max(max_events, 1);
+    int64_t P = std::max<int64_t>(max_pixels, 1), C = std::max<int64_t>(max_clusters, 1), min_pool = want_pool;
+    if (c->ws) {  // keep what the old reservation covered
+        E = std::max(E, c->w.cap_events);
+        P = std::max(P, c->w.cap_pixels);
+        C = std::max(C, c->w.cap_clusters);
+        min_pool = std::max(min_pool, c->w.pool_cap);
+    }
     HIP_OK(hipSetDevice(c->device));
     if (c->ws) {
         HIP_OK(hipDeviceSynchronize());
@@ -364,12 +382,10 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
         c->ws = nullptr;
     }
     Work w{};
-    const size_t bytes = layout(w, nullptr, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
-                                std::max<int64_t>(max_clusters, 1), c->n_cu);
+    const size_t bytes = layout(w, nullptr, E, P, C, c->n_cu, min_pool);
     void* base = nullptr;
     HIP_OK(hipMalloc(&base, bytes));
-    layout(w, (char*)base, std::max(max_events, 1), std::max<int64_t>(max_pixels, 1),
-           std::max<int64_t>(max_clusters, 1), c->n_cu);
+    layout(w, (char*)base, E, P, C, c->n_cu, min_pool);
     c->w = w;
     c->ws = base;
     c->ws_bytes = bytes;
@@ -688,7 +704,10 @@ int velo_seed_filter_set(velo_ctx* c, const float* h_weights, const float* h_nor
         d[kSeedW3 + o] = h_weights[kSeedIn * kSeedH + 2 * kSeedH + kSeedH * kSeedH + o];
     }
     d[kSeedB3] = h_weights[kSeedIn * kSeedH + 3 * kSeedH + kSeedH * kSeedH];
-    for (int i = 0; i < 2 * kSeedIn; ++i) d[kSeedNorm + i] = h_norm[i];
+    for (int i = 0; i < kSeedIn; ++i) {
+        d[kSeedNorm + i] = h_norm[i];
+        d[kSeedNorm + kSeedIn + i] = 1.0f / h_norm[kSeedIn + i];  // FP32, as the network defines it
+    }
     d[kSeedThr] = threshold;
     HIP_OK(hipSetDevice(c->device));
     HIP_OK(hipMemcpy(c->d_seed, d.data(), sizeof(float) * kSeedFloats, hipMemcpyHostToDevice));

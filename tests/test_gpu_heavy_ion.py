@@ -97,3 +97,26 @@ def test_fused_pipeline(event):
             "trk_hit": np_(bufs["trk_hit"], H), "trk_planes": np_(bufs["trk_planes"], T, np.uint32),
             "trk_flags": np_(bufs["trk_flags"], T),
         })
+
+
+def test_context_first_reserved_for_many_small_events(event):
+    """A context reserved for 1000 nominal-size events, then for this one event:
+    the counts fit the old workspace, but its large-event candidate pool was
+    sized for small events, so velo_reserve must lay it out again."""
+    velo, b = event
+    cut = cuts(GOLD["cuts"])
+    v = velo.Velo(b.plane_z, cut)
+    v.reserve(1000, 6_000_000, 6_000_000)
+    v.reserve(b.n_events, b.n_pix, b.n_pix)
+    off, ids = velo.to_device(b)
+    c = v.cluster(off, ids, with_npix=False)
+    n_clu = int(c["clu_off"][-1].item())
+    t = v.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], n_clu=n_clu)
+    torch.cuda.synchronize()
+    st = v.read_status(t["status"])
+    assert st[0] == 0, st[:8]
+    T = int(t["trk_off"][-1].item())
+    H = int(t["trk_hit_off"][T].item())
+    assert (T, H) == (GOLD["n_tracks"], GOLD["n_hits"])
+    check_digests({"trk_hit_off": np_(t["trk_hit_off"], T + 1), "trk_hit": np_(t["trk_hit"], H),
+                   "trk_planes": np_(t["trk_planes"], T, np.uint32)})
