@@ -150,6 +150,9 @@ struct LdsStore {
     // enumeration scratch (seeding slots are free before the claiming rounds)
     __device__ int32_t* pref() { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
     __device__ int32_t* ebuf() { return reinterpret_cast<int32_t*>(&t->slota[0][0]); }
+    // seed-filter broadcast scratch, 2 kT floats (the seeding slots, still free)
+    __device__ float* bcast() { return reinterpret_cast<float*>(&t->slota[0][0]); }
+    static_assert(sizeof(uint64_t) * 3 * kP >= sizeof(float) * 2 * kT, "broadcast scratch fits the slots");
     __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
     __device__ int16_t& twant(int i) { return t->twant[i]; }
     __device__ float& cq(int i) { return t->cq[i]; }
@@ -179,6 +182,7 @@ struct GlobalStore {
     int seed_k = 0;  // plane of h0 during seeding
     const float* seedw = nullptr;  // seed network in LDS, rows [unit][input] (seed variant)
     float* seedh = nullptr;        // per-thread first-layer activations in LDS, [unit][thread]
+    __device__ float* bcast() { return seedh; }  // seed-filter broadcast scratch (>= 2 kT floats)
     __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
     __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
     __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
@@ -1052,20 +1056,19 @@ __device__ __forceinline__ void seed_features(S& st, const Params& p, int k, int
 // The network evaluates in FP32 in one fixed order: features standardised as
 // (f - mean) * (1 / sd), each unit starts from its bias and adds weight x input
 // for inputs in ascending order, ReLU between layers.  Two layouts of the same
-// arithmetic: a half-wave per candidate (lane o holds hidden unit o, inputs
-// broadcast across the half-wave), and -- in the large-event finder, whose
+// arithmetic: a half-wave per candidate (lane o holds hidden unit o, its
+// outputs broadcast to the half-wave through LDS), and -- in the large-event finder, whose
 // crowded plane steps bring thousands of candidates -- one candidate per lane
 // with the weights read from an LDS copy as uniform operands.  A candidate
 // whose logit exceeds the threshold dies.
 template <int kT, class S>
-__device__ void seed_filter(S& st, const FindArgs& a, int k) {
+__device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __restrict__ W) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
     const int nc = sc.n_cand;
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const float fn[4] = {(float)k, (float)(sc.cb[k + 1] - sc.cb[k]), (float)(sc.cb[k + 2] - sc.cb[k + 1]),
                          (float)(sc.cb[k + 3] - sc.cb[k + 2])};
-    const float* W = a.seed_net;
     const bool on = W != nullptr;
     auto emit = [&](const float* f, int i0, int i1, int i2) {
         const unsigned long long slot = atomicAdd(a.seed_count, 1ull);
@@ -1109,11 +1112,12 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k) {
             }
         }
     } else {
-        const int lane = threadIdx.x & (kWave - 1);
-        const int o = lane & (kSeedH - 1);
-        const int hb = lane & kSeedH;  // first lane of this half-wave
+        const int o = threadIdx.x & (kSeedH - 1);
         constexpr int kGroups = kT / kSeedH;
         static_assert(kWave == 2 * kSeedH, "two candidates per wave");
+        // this half-wave's 32 activations of each layer, broadcast through LDS
+        float* b1 = st.bcast() + (threadIdx.x / kSeedH) * kSeedH;
+        float* b2 = b1 + kT;
         for (int c0 = 0; c0 < nc; c0 += kGroups) {
             const int c = c0 + (int)threadIdx.x / kSeedH;
             const bool valid = c < nc;
@@ -1123,22 +1127,28 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k) {
             seed_features(st, p, k, valid ? c : nc - 1, fn, f, &i0, &i1, &i2);
             if (a.seed_feat && valid && o == 0) emit(f, i0, i1, i2);
             if (!on) continue;
-            // weights re-read (L1 / scalar cache) per candidate rather than
-            // held in registers across the loop
-            const float* Wc = W;
-            asm volatile("" : "+s"(Wc));
-            float h = Wc[kSeedB1 + o];
+            // the per-lane weight rows are re-read each round (L1) rather than
+            // held in registers across the loop; the uniform ones come
+            // through the scalar cache
+            const float* Wl = W;
+            asm volatile("" : "+s"(Wl));
+            typedef const __attribute__((address_space(1))) float* gptr;
+            const gptr Wg = (gptr)Wl;
+            float h = Wg[kSeedB1 + o];
             for (int i = 0; i < kSeedIn; ++i) {
-                const float xs = (f[i] - Wc[kSeedNorm + i]) * Wc[kSeedNorm + kSeedIn + i];
-                h = h + Wc[kSeedW1T + i * kSeedH + o] * xs;
+                const float xs = (f[i] - W[kSeedNorm + i]) * W[kSeedNorm + kSeedIn + i];
+                h = h + Wg[kSeedW1T + i * kSeedH + o] * xs;
             }
-            const float h1 = h > 0.0f ? h : 0.0f;
-            h = Wc[kSeedB2 + o];
-            for (int i = 0; i < kSeedH; ++i) h = h + Wc[kSeedW2T + i * kSeedH + o] * __shfl(h1, hb + i);
-            const float h2 = h > 0.0f ? h : 0.0f;
-            float z = Wc[kSeedB3];
-            for (int i = 0; i < kSeedH; ++i) z = z + Wc[kSeedW3 + i] * __shfl(h2, hb + i);
-            if (valid && o == 0 && z > Wc[kSeedThr]) st.calive(c) = 0;
+            b1[o] = h > 0.0f ? h : 0.0f;
+            group_sync<kWave, kT>();
+            h = Wg[kSeedB2 + o];
+            for (int i = 0; i < kSeedH; ++i) h = h + Wg[kSeedW2T + i * kSeedH + o] * b1[i];
+            b2[o] = h > 0.0f ? h : 0.0f;
+            group_sync<kWave, kT>();
+            float z = W[kSeedB3];
+            for (int i = 0; i < kSeedH; ++i) z = z + W[kSeedW3 + i] * b2[i];
+            if (valid && o == 0 && z > W[kSeedThr]) st.calive(c) = 0;
+            group_sync<kWave, kT>();  // the next round rewrites b1 and b2
         }
     }
     __syncthreads();
@@ -1147,7 +1157,7 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k) {
 // Whole event.  Returns false when a capacity was too small (LDS tile: redo on
 // the large path; large path: overflow); on true the candidates are final.
 template <int kT, bool kSeed, class S>
-__device__ bool find_event(S& st, const FindArgs& a, int e) {
+__device__ bool find_event(S& st, const FindArgs& a, int e, const float* __restrict__ seed_net) {
     Scalars& sc = *st.s;
     if (threadIdx.x == 0) {
         sc.n_tracks = 0;
@@ -1177,7 +1187,7 @@ __device__ bool find_event(S& st, const FindArgs& a, int e) {
             if (!enumerate_seeds<kT>(st, a, k)) return false;
             PHASE(2);
             if (sc.n_cand > 0) {
-                if constexpr (kSeed) seed_filter<kT>(st, a, k);
+                if constexpr (kSeed) seed_filter<kT>(st, a, k, seed_net);
                 claim_seeds<kT>(st, a, k);
                 PHASE(3);
                 if (!create_tracks<kT>(st, a, k)) return false;
@@ -1200,8 +1210,10 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
 
 // kSeed: the variant with the seed filter / emission (separate code, so that
 // the plain finder keeps its register allocation and occupancy).
+// seed_net: the seed network (null: none), a separate read-only argument so that
+// its uniform weights load through the scalar cache.
 template <int kT, int kP, int kTr, int kC, bool kSeed>
-__global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) {
+__global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a, const float* __restrict__ seed_net) {
     __shared__ Tile<kP, kTr, kC> tile;
     __shared__ Scalars sc;
     LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
@@ -1226,7 +1238,7 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) 
         bool ok = false;
         if (!big) {
             st.slot0 = a.clu_off[e * kPlanes];
-            ok = find_event<kT, kSeed>(st, a, e);
+            ok = find_event<kT, kSeed>(st, a, e, seed_net);
         }
         if (!ok && threadIdx.x == 0) {
             const int i = atomicAdd(a.w.counters + 2, 1);
@@ -1237,7 +1249,7 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a) 
 }
 
 template <int kT, bool kSeed>
-__global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
+__global__ __launch_bounds__(kT) void k_find_large(FindArgs a, const float* __restrict__ seed_net) {
     __shared__ Scalars sc;
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
     __shared__ __align__(16) float seedw[kSeed ? kSeedFloats : 1];
@@ -1247,15 +1259,15 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
     st.seedh = seedh;
     if constexpr (kSeed) {
         // the seed network with its weight matrices back in [unit][input] rows
-        if (a.seed_net) {
+        if (seed_net) {
             for (int i = threadIdx.x; i < kSeedFloats; i += kT) {
-                float v = a.seed_net[i];
+                float v = seed_net[i];
                 if (i < kSeedB1) {
                     const int o = i / kSeedIn, j = i % kSeedIn;
-                    v = a.seed_net[kSeedW1T + j * kSeedH + o];
+                    v = seed_net[kSeedW1T + j * kSeedH + o];
                 } else if (i >= kSeedW2T && i < kSeedB2) {
                     const int o = (i - kSeedW2T) / kSeedH, j = (i - kSeedW2T) % kSeedH;
-                    v = a.seed_net[kSeedW2T + j * kSeedH + o];
+                    v = seed_net[kSeedW2T + j * kSeedH + o];
                 }
                 seedw[i] = v;
             }
@@ -1298,7 +1310,7 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a) {
         st.slot0 = c0;
         st.cap_t = (int)((c1 - c0) / 3 + 1);
         __syncthreads();
-        const bool ok = find_event<kT, kSeed>(st, a, e);
+        const bool ok = find_event<kT, kSeed>(st, a, e, seed_net);
         if (!ok && threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
         __syncthreads();
     }
@@ -1361,9 +1373,9 @@ bool seed_variant(const FindArgs& a) { return a.seed_net != nullptr || a.seed_fe
 template <int kT, int kP, int kTr, int kC>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
     if (seed_variant(a))
-        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, true>), dim3(grid), dim3(kT), 0, s, a);
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, true>), dim3(grid), dim3(kT), 0, s, a, a.seed_net);
     else
-        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, false>), dim3(grid), dim3(kT), 0, s, a);
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, false>), dim3(grid), dim3(kT), 0, s, a, nullptr);
     return hipGetLastError();
 }
 
@@ -1411,9 +1423,9 @@ int find_blocks_per_cu(int threads, int tile, bool seed) {
 
 hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
     if (seed_variant(a))
-        hipLaunchKernelGGL((k_find_large<256, true>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_find_large<256, true>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a, a.seed_net);
     else
-        hipLaunchKernelGGL((k_find_large<256, false>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_find_large<256, false>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a, nullptr);
     return hipGetLastError();
 }
 
