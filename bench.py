@@ -5,7 +5,9 @@ Workload (the nominal-occupancy configuration): 1000 synthetic events, Poisson(5
 primary vertices x Poisson(40) tracks, 1 mrad scattering per plane, calibrated
 noise giving ~3k clusters per event (seed 1002).  One step = the whole path
 (clustering + staging, track finding, acceptance, CSR output, fit) over the
-batch, inputs resident in HBM, launched as one replayed HIP graph.
+batch, inputs resident in HBM, launched as one replayed HIP graph; by default three batches are in flight, each
+on its own context, buffers and HIP stream (--streams), so that one batch's
+clustering and output overlap the tail of another's track finding.
 
 Prints ONE JSON line: events/s, the dominant kernel's HBM roofline fraction
 (algorithmic bytes / its HIP-event-timed duration), efficiency / ghost rate of
@@ -101,6 +103,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["plain", "learned"], default="plain")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="batches in flight: each on its own context, buffers and HIP stream")
     ap.add_argument("--seed-filter", action="store_true",
                     help="seed-level learned filter with the committed network (configs/seed_default.npz)")
     ap.add_argument("--path", choices=["fused", "three-call"], default="fused",
@@ -139,7 +143,6 @@ def main():
 
     seed_net = None
     if args.seed_filter:
-        import numpy as np
         d = np.load(os.path.join(cfg, "seed_default.npz"), allow_pickle=False)
         seed_net = (d["weights"].astype(np.float32), d["norm"].astype(np.float32), float(d["threshold"]))
 
@@ -156,12 +159,16 @@ def main():
         from paper_2412_05041_amd import learned
         master, norm = learned.load_default_weights()
         cuts = dict(cuts, mode=1, logit_band=learned.DEFAULT_BAND)
-    v = velo.Velo(batch.plane_z, cuts, device=0)
-    if args.mode == "learned":
-        v.mlp_set_weights(master, norm)
-    if seed_net is not None:
-        v.seed_filter_set(*seed_net)
-    v.reserve(E, batch.n_pix, batch.n_pix)
+    def new_context():
+        c = velo.Velo(batch.plane_z, cuts, device=0)
+        if args.mode == "learned":
+            c.mlp_set_weights(master, norm)
+        if seed_net is not None:
+            c.seed_filter_set(*seed_net)
+        c.reserve(E, batch.n_pix, batch.n_pix)
+        return c
+
+    v = new_context()
     off, ids = velo.to_device(batch)
     tune_ms = None
     if args.launch:
@@ -173,45 +180,80 @@ def main():
         del c
     else:
         tune_ms = None
-    bufs = v.pipeline_buffers(E, batch.n_pix)
-    torch.cuda.synchronize()
-    log(f"launch {v.get_launch()}, warm-up")
 
-    path_step = v.pipeline if args.path == "fused" else v.three_call
-    kal_out = None
-    if args.kalman is not None:
-        kal_out = torch.empty((max(bufs["trk_cap"], 1), 16), dtype=torch.float32, device=v.device)
-
-    def kalman():
-        v.kalman_fit(bufs["trk_hit_off"], bufs["trk_hit"], bufs["trk_planes"], bufs["clu_x"], bufs["clu_y"],
-                     args.kalman, max_tracks=bufs["trk_cap"], d_n_tracks=bufs["trk_off"][E:], out=kal_out)
-
-    dec = None
+    bank = None
     if args.raw:
         bank_off, bank = gen.raw_banks(batch, seed=w.seed)
         d_bank_off = torch.from_numpy(bank_off).to(v.device)
         d_bank = torch.from_numpy(bank.view(np.int32)).to(v.device)
-        dec = v.decode(d_bank_off, d_bank, batch.n_pix)
-        dec_ids = dec["pix_id"][:batch.n_pix]
         log(f"raw banks: {bank.size} words for {batch.n_pix} pixels")
 
-    def step(o, i, b):
-        if dec is not None:
-            v.decode(d_bank_off, d_bank, batch.n_pix, out=dec)
-            o, i = dec["pix_off"], dec_ids
-        path_step(o, i, b)
-        if kal_out is not None:
-            kalman()
-    for _ in range(args.warmup):
-        step(off, ids, bufs)
+    class Lane:
+        """One batch in flight: a context (workspace, graph), its buffers, its stream."""
+
+        def __init__(self, ctx):
+            self.v = ctx
+            self.bufs = ctx.pipeline_buffers(E, batch.n_pix)
+            self.stream = torch.cuda.Stream()
+            self.kal_out = None
+            if args.kalman is not None:
+                self.kal_out = torch.empty((max(self.bufs["trk_cap"], 1), 16), dtype=torch.float32,
+                                           device=ctx.device)
+            self.dec = None
+            if bank is not None:
+                self.dec = ctx.decode(d_bank_off, d_bank, batch.n_pix)
+                self.dec_ids = self.dec["pix_id"][:batch.n_pix]
+
+        def kalman(self):
+            b = self.bufs
+            self.v.kalman_fit(b["trk_hit_off"], b["trk_hit"], b["trk_planes"], b["clu_x"], b["clu_y"], args.kalman,
+                              max_tracks=b["trk_cap"], d_n_tracks=b["trk_off"][E:], out=self.kal_out)
+
+        def step(self):
+            o, i = off, ids
+            if self.dec is not None:
+                self.v.decode(d_bank_off, d_bank, batch.n_pix, out=self.dec)
+                o, i = self.dec["pix_off"], self.dec_ids
+            (self.v.pipeline if args.path == "fused" else self.v.three_call)(o, i, self.bufs)
+            if self.kal_out is not None:
+                self.kalman()
+
+    lanes = [Lane(v)]
+    th0, tl0 = v.get_launch()
+    for _ in range(args.streams - 1):
+        c = new_context()
+        c.set_launch(th0, tl0)
+        lanes.append(Lane(c))
+    torch.cuda.synchronize()
+    log(f"launch {v.get_launch()}, {args.streams} batch(es) in flight, warm-up")
+
+    cur = torch.cuda.current_stream()
+
+    def run(n):
+        # batch k goes to lane k mod N; a lane's batches run in order on its stream
+        for L in lanes:
+            L.stream.wait_stream(cur)
+        for k in range(n):
+            L = lanes[k % len(lanes)]
+            with torch.cuda.stream(L.stream):
+                L.step()
+        for L in lanes:
+            cur.wait_stream(L.stream)
+
+    run(max(args.warmup, len(lanes)))
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(off, ids, bufs)
+    run(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * E / dt
+    for L in lanes[1:]:
+        assert L.v.read_status(L.bufs["status"])[0] == 0
+    bufs = lanes[0].bufs
+    dec = lanes[0].dec
+    kal_out = lanes[0].kal_out
+    kalman = lanes[0].kalman
     st = v.read_status(bufs["status"])
     if args.path == "three-call":
         stc = v.read_status(bufs["status_clu"])
@@ -301,6 +343,7 @@ def main():
             "raw_banks": bool(args.raw),
             "launch": {"threads_per_event": th, "tile": tl},
             "autotune_ms": tune_ms,
+            "batches_in_flight": args.streams,
         },
         "efficiency": m["efficiency"],
         "ghost_rate": m["ghost_rate"],
