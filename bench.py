@@ -357,6 +357,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(dom, (th, tl), w.name),
             "alg_bytes": alg[dom],
+            "launch_ms": stages[dom],
+            "launch_timing": "HIP events around the kernel on its stream, one batch in flight",
         },
         "path_hbm_frac": path_bytes / E * value / (HBM_PEAK_GBS * 1e9),
         "stages_ms": stages,
