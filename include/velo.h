@@ -73,7 +73,8 @@ enum velo_event_flag {
     VELO_EV_OVERFLOW = 1,  /* an output or internal capacity was exceeded: no tracks */
     VELO_EV_BAD_INPUT = 2, /* malformed pixel input (validate mode)                   */
     VELO_EV_LARGE_PATH = 4, /* processed by the large-event (global memory) path      */
-    VELO_EV_FALLBACK = 8   /* learned mode: some decision used the plain cut          */
+    VELO_EV_FALLBACK = 8,  /* learned mode: some decision used the plain cut          */
+    VELO_EV_SECOND_TILE = 16 /* did not fit the configured LDS tile: next larger tile */
 };
 
 enum velo_track_flag {
@@ -202,7 +203,8 @@ int velo_pipeline(velo_ctx* ctx, int32_t n_events, const int32_t* d_pix_off, con
  * graph) with HIP events recorded on `stream` between the stages; after the
  * call velo_last_timing synchronises the stream and returns the durations (ms)
  * of the VELO_N_STAGES stages: reset, cluster+staging, event order, finder
- * (LDS tiles), finder (large events), acceptance (+ learned decision), scan,
+ * (configured LDS tile), finder (events that did not fit it: the next larger
+ * LDS tile, then global memory), acceptance (+ learned decision), scan,
  * output+fit. */
 #define VELO_N_STAGES 8
 int velo_set_timing(velo_ctx* ctx, int32_t on);

@@ -46,7 +46,7 @@ struct Params {
     float r_ext;    // >= sqrt(e_max)
 };
 
-enum : int { EV_OVERFLOW = 1, EV_BAD_INPUT = 2, EV_LARGE = 4, EV_FALLBACK = 8 };
+enum : int { EV_OVERFLOW = 1, EV_BAD_INPUT = 2, EV_LARGE = 4, EV_FALLBACK = 8, EV_TILE2 = 16 };
 enum : int { TRK_PLAIN = 1, TRK_LEARNED = 2, TRK_FALLBACK = 4, TRK_ACCEPT = 8 };
 enum : int { ST_SEVERITY = 0, ST_NCLU = 1, ST_NTRK = 2, ST_NHIT = 3, ST_NPIX = 4, ST_NLARGE = 5,
              ST_NFALLBACK = 6, ST_MAXCAND = 7 };
@@ -83,9 +83,11 @@ struct Work {
     int32_t* ev_tbase;    // exclusive scans of ev_nout / ev_nouthit
     int32_t* ev_hbase;
     int32_t* order;       // event processing order (largest first)
-    int32_t* large;       // events for the large-event path
+    int32_t* large;       // events that did not fit the first LDS tile
+    int32_t* large2;      // events that did not fit the second LDS tile either
     int32_t* seg_m;       // clusters per (event, plane) segment
-    int32_t* counters;    // [1] finder events, [2] #large, [3] large tickets, others spare
+    int32_t* counters;    // [1] finder events, [2] #large, [3] large-path tickets, [4] second-tile
+                          // tickets, [5] #large2, others spare
     // large-event path, per cluster (global cluster index)
     int32_t* g_claim;
     uint64_t* g_slota;

@@ -1219,12 +1219,14 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a, 
     LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
     while (true) {
         if (threadIdx.x == 0) {
-            const int i = atomicAdd(a.w.counters + 1, 1);
-            sc.event = i < a.n_events ? a.w.order[i] : -1;
+            const int n = a.q_count < 0 ? a.n_events : a.w.counters[a.q_count];
+            const int i = atomicAdd(a.w.counters + a.q_cursor, 1);
+            sc.event = i < n ? a.q_in[i] : -1;
         }
         __syncthreads();
         const int e = sc.event;
         if (e < 0) return;
+        if (a.q_count >= 0 && threadIdx.x == 0 && a.status) atomicOr(a.status + kStatusHdr + e, EV_TILE2);
         if (a.clu_off[(e + 1) * kPlanes] > a.clu_limit) {  // clusters not (all) available
             if (threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
             __syncthreads();
@@ -1241,8 +1243,8 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a, 
             ok = find_event<kT, kSeed>(st, a, e, seed_net);
         }
         if (!ok && threadIdx.x == 0) {
-            const int i = atomicAdd(a.w.counters + 2, 1);
-            a.w.large[i] = e;
+            const int i = atomicAdd(a.w.counters + a.q_out_count, 1);
+            a.q_out[i] = e;
         }
         __syncthreads();
     }
@@ -1276,11 +1278,11 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a, const float* __re
         __syncthreads();
     }
     st.cell = a.w.g_cell + (int64_t)blockIdx.x * kCellWords;
-    const int n_large = a.w.counters[2];
+    const int n_large = a.w.counters[a.q_count];
     while (true) {
         if (threadIdx.x == 0) {
-            const int i = atomicAdd(a.w.counters + 3, 1);
-            sc.event = i < n_large ? a.w.large[i] : -1;
+            const int i = atomicAdd(a.w.counters + a.q_cursor, 1);
+            sc.event = i < n_large ? a.q_in[i] : -1;
         }
         __syncthreads();
         const int e = sc.event;
@@ -1395,7 +1397,7 @@ int occ_lds(bool seed) {
     X(T, 1, 512, 640, 640)             \
     X(T, 2, 1024, 1024, 1024)
 
-hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
+static hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
 #define VELO_CASE(T, L, P, TR, C) \
     case T * 4 + L: return launch_lds<T, P, TR, C>(a, grid, s);
     switch (threads * 4 + tile) {
@@ -1421,12 +1423,37 @@ int find_blocks_per_cu(int threads, int tile, bool seed) {
 #undef VELO_CASE
 }
 
-hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
+static hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
     if (seed_variant(a))
         hipLaunchKernelGGL((k_find_large<256, true>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a, a.seed_net);
     else
         hipLaunchKernelGGL((k_find_large<256, false>), dim3(a.w.n_large_blocks), dim3(256), 0, s, a, nullptr);
     return hipGetLastError();
+}
+
+hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid0, hipStream_t s) {
+    a.q_in = a.w.order;
+    a.q_count = -1;
+    a.q_cursor = 1;
+    a.q_out = a.w.large;
+    a.q_out_count = 2;
+    return launch_find_lds(a, threads, tile, grid0, s);
+}
+
+hipError_t launch_finder_rest(FindArgs a, int threads, int tile, int grid1, hipStream_t s) {
+    a.q_in = a.w.large;
+    a.q_count = 2;
+    if (tile < 2) {
+        a.q_cursor = 4;
+        a.q_out = a.w.large2;
+        a.q_out_count = 5;
+        const hipError_t e = launch_find_lds(a, threads, tile + 1, grid1, s);
+        if (e != hipSuccess) return e;
+        a.q_in = a.w.large2;
+        a.q_count = 5;
+    }
+    a.q_cursor = 3;
+    return launch_find_large(a, s);
 }
 
 #ifdef VELO_PHASE_TIMING

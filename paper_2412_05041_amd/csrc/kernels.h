@@ -40,6 +40,12 @@ struct FindArgs {
     const float* mlp_master;  // learned mode: FP32 master weights (device)
     const float* mlp_norm;    // 20 floats
     int64_t clu_limit;        // events whose clusters reach beyond this are not processed
+    // event queue of an LDS-tile pass: events q_in[0 .. n) with n = n_events
+    // (q_count < 0) or counters[q_count], taken through counters[q_cursor];
+    // events that do not fit go to q_out, counted in counters[q_out_count]
+    const int32_t* q_in;
+    int q_count, q_cursor, q_out_count;
+    int32_t* q_out;
     const float* seed_net;    // seed filter network, kSeedFloats (null: no seed filter)
     float* seed_feat;         // seed emission for training: [seed_cap][10] features (null: off)
     int32_t* seed_hits;       // [seed_cap][3] global cluster indices
@@ -108,8 +114,12 @@ hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_
 hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s);
 hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s);
-hipError_t launch_find_large(const FindArgs& a, hipStream_t s);
+// The finder in two enqueues: the LDS-tile pass of the configured tile over all
+// events (grid0 workgroups, persistent); then a second LDS pass with the next
+// larger tile over the events that did not fit (tiles 0 and 1; grid1), and the
+// global-memory finder over what is left.
+hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid0, hipStream_t s);
+hipError_t launch_finder_rest(FindArgs a, int threads, int tile, int grid1, hipStream_t s);
 hipError_t launch_accept(const FindArgs& a, hipStream_t s);
 hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);

@@ -144,6 +144,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, in
     w.ev_hbase = carve<int32_t>(cur, E);
     w.order = carve<int32_t>(cur, E);
     w.large = carve<int32_t>(cur, E);
+    w.large2 = carve<int32_t>(cur, E);
     w.seg_m = carve<int32_t>(cur, (int64_t)E * kPlanes);
     w.counters = carve<int32_t>(cur, 8);
     w.g_claim = carve<int32_t>(cur, C);
@@ -188,10 +189,21 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, in
     return (size_t)(cur - base) + 256;
 }
 
-int grid_for(velo_ctx* c, int n_events) {
-    const int per_cu = find_blocks_per_cu(c->threads, c->tile, c->seed_on || c->seed_feat);
+int grid_for(velo_ctx* c, int n_events, int threads, int tile) {
+    const int per_cu = find_blocks_per_cu(threads, std::min(tile, 2), c->seed_on || c->seed_feat);
     const int g = std::max(1, c->n_cu * std::min(std::max(per_cu, 1), kMaxLdsBlocksPerCu));
     return std::max(1, std::min(n_events, g));
+}
+
+// The second LDS pass gets the events too large for the first tile: the
+// heaviest of the batch, few of them, so it always runs 512 threads per event.
+constexpr int kSecondPassThreads = 512;
+
+hipError_t enqueue_finder(velo_ctx* c, const FindArgs& fa, int E, hipStream_t s) {
+    const hipError_t e = launch_finder_first(fa, c->threads, c->tile, grid_for(c, E, c->threads, c->tile), s);
+    return e != hipSuccess ? e
+                           : launch_finder_rest(fa, kSecondPassThreads, c->tile,
+                                                grid_for(c, E, kSecondPassThreads, c->tile + 1), s);
 }
 
 // Enqueue the finder (staging must be in place) and the output compaction.
@@ -223,9 +235,9 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     fa.seed_hits = c->seed_hits;
     fa.seed_cap = c->seed_cap;
     fa.seed_count = c->seed_count;
-    HIP_OK(launch_find_lds(fa, c->threads, c->tile, grid_for(c, E), s));
+    HIP_OK(launch_finder_first(fa, c->threads, c->tile, grid_for(c, E, c->threads, c->tile), s));
     if (int rc = mark(c, 4, s, timed)) return rc;
-    HIP_OK(launch_find_large(fa, s));
+    HIP_OK(launch_finder_rest(fa, kSecondPassThreads, c->tile, grid_for(c, E, kSecondPassThreads, c->tile + 1), s));
     if (int rc = mark(c, 5, s, timed)) return rc;
     HIP_OK(launch_accept(fa, s));
     if (c->p.mode == 1) HIP_OK(launch_mlp_accept(c->mlp, fa, s));
@@ -629,8 +641,7 @@ int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* c
                 HIP_OK(launch_reset(c->w, E, nullptr, s));
                 HIP_OK(launch_order(c->w, E, clu_off, s));
                 HIP_OK(hipEventRecord(e0, s));
-                HIP_OK(launch_find_lds(fa, c->threads, c->tile, grid_for(c, E), s));
-                HIP_OK(launch_find_large(fa, s));
+                HIP_OK(enqueue_finder(c, fa, E, s));
                 HIP_OK(hipEventRecord(e1, s));
                 HIP_OK(hipEventSynchronize(e1));
                 float ms = 0.0f;

@@ -19,7 +19,7 @@ N_PLANES = 26
 N_LAUNCH = 12  # finder launch configurations timed by the autotuner
 N_PARAM = 1441
 STATUS_HDR = 8
-EV_OVERFLOW, EV_BAD_INPUT, EV_LARGE_PATH, EV_FALLBACK = 1, 2, 4, 8
+EV_OVERFLOW, EV_BAD_INPUT, EV_LARGE_PATH, EV_FALLBACK, EV_SECOND_TILE = 1, 2, 4, 8, 16
 TRK_PLAIN_ACCEPT, TRK_LEARNED, TRK_FALLBACK, TRK_ACCEPT = 1, 2, 4, 8
 
 

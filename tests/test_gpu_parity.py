@@ -150,8 +150,8 @@ def test_every_launch_configuration_gives_identical_tracks(velo_mod, threads, ti
     st = v.read_status(bufs["status"])
     assert st[0] == 0
     assert_tracks_equal(bufs, t, check_flags=True)
-    if tile == 0:
-        assert st[5] > 0  # planes above 256 hits went through the large-event path
+    if tile == 0:  # planes above 256 hits went through the second (512) tile
+        assert np.any(st[8:8 + b.n_events] & velo_mod.EV_SECOND_TILE)
 
 
 def test_large_event_path_on_dense_events(velo_mod):
