@@ -328,12 +328,18 @@ def main():
         kbytes = 12 * H + 72 * T  # hit index + x, y per hit; offset, planes, 16-float state per track
         kal = {"ms": kms, "alg_bytes": kbytes, "achieved_GBs": kbytes / (kms * 1e-3) / 1e9,
                "frac": kbytes / (kms * 1e-3) / (HBM_PEAK_GBS * 1e9), "ms_noise": args.kalman}
-    dom = max(("cluster", "find_lds", "find_large", "accept", "output_fit"), key=lambda k: stages[k])
+    # dominant kernel: the largest share of the batch's device time -- its
+    # duration, for the finder passes weighted by the fraction of the events
+    # they process (the second pass takes a few hundred workgroups, not the GPU)
+    ev_rest = (st[8:8 + E] & (velo.EV_SECOND_TILE | velo.EV_LARGE_PATH)) != 0
+    share = dict(stages)
+    share["find_lds"] = stages["find_lds"] * (1.0 - ev_rest.mean())
+    share["find_large"] = stages["find_large"] * ev_rest.mean()
+    dom = max(("cluster", "find_lds", "find_large", "accept", "output_fit"), key=lambda k: share[k])
     # algorithmic bytes per launch (minimum traffic the stage must move)
     n_pix = batch.n_pix
     # the finder's two stages split the events: those that fit the configured
     # LDS tile, and those that went on to the larger tile or global memory
-    ev_rest = (st[8:8 + E] & (velo.EV_SECOND_TILE | velo.EV_LARGE_PATH)) != 0
     clu_ev = np.diff(clu_off[::26].astype(np.int64))
     trk_off_h = bufs["trk_off"].cpu().numpy().astype(np.int64)
     hit_off_h = bufs["trk_hit_off"][:T + 1].cpu().numpy().astype(np.int64)

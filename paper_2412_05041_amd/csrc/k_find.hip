@@ -1226,7 +1226,7 @@ __global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a, 
         __syncthreads();
         const int e = sc.event;
         if (e < 0) return;
-        if (a.q_count >= 0 && threadIdx.x == 0 && a.status) atomicOr(a.status + kStatusHdr + e, EV_TILE2);
+        if (a.q_in == a.w.large && threadIdx.x == 0 && a.status) atomicOr(a.status + kStatusHdr + e, EV_TILE2);
         if (a.clu_off[(e + 1) * kPlanes] > a.clu_limit) {  // clusters not (all) available
             if (threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
             __syncthreads();
@@ -1288,6 +1288,11 @@ __global__ __launch_bounds__(kT) void k_find_large(FindArgs a, const float* __re
         const int e = sc.event;
         if (e < 0) return;
         const int64_t c0 = a.clu_off[e * kPlanes], c1 = a.clu_off[(e + 1) * kPlanes];
+        if (c1 > a.clu_limit) {  // clusters not (all) available
+            if (threadIdx.x == 0) write_empty(a, e, EV_OVERFLOW);
+            __syncthreads();
+            continue;
+        }
         int too_big = 0;
         for (int k = threadIdx.x; k < kPlanes; k += kT)
             too_big |= (a.clu_off[e * kPlanes + k + 1] - a.clu_off[e * kPlanes + k]) > 65535;
@@ -1431,27 +1436,37 @@ static hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid0, hipStream_t s) {
-    a.q_in = a.w.order;
-    a.q_count = -1;
-    a.q_cursor = 1;
-    a.q_out = a.w.large;
-    a.q_out_count = 2;
-    return launch_find_lds(a, threads, tile, grid0, s);
+int tile_planes(int tile) {
+#define VELO_CASE(T, L, P, TR, C) \
+    case L: return P;
+    switch (tile) {
+        VELO_TILES(VELO_CASE, 0)
+        default: return 0;
+    }
+#undef VELO_CASE
 }
 
-hipError_t launch_finder_rest(FindArgs a, int threads, int tile, int grid1, hipStream_t s) {
+hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid, hipStream_t s) {
+    a.q_in = a.w.order;
+    a.q_count = 6;
+    a.q_cursor = 1;
+    a.q_out = a.w.large2;
+    a.q_out_count = 5;
+    return launch_find_lds(a, threads, tile, grid, s);
+}
+
+hipError_t launch_finder_second(FindArgs a, int tile, int grid, hipStream_t s) {
     a.q_in = a.w.large;
     a.q_count = 2;
-    if (tile < 2) {
-        a.q_cursor = 4;
-        a.q_out = a.w.large2;
-        a.q_out_count = 5;
-        const hipError_t e = launch_find_lds(a, threads, tile + 1, grid1, s);
-        if (e != hipSuccess) return e;
-        a.q_in = a.w.large2;
-        a.q_count = 5;
-    }
+    a.q_cursor = 4;
+    a.q_out = a.w.large2;
+    a.q_out_count = 5;
+    return launch_find_lds(a, kSecondPassThreads, tile, grid, s);
+}
+
+hipError_t launch_finder_large(FindArgs a, hipStream_t s) {
+    a.q_in = a.w.large2;
+    a.q_count = 5;
     a.q_cursor = 3;
     return launch_find_large(a, s);
 }

@@ -21,28 +21,43 @@ __global__ void k_reset(Work w, int n_events, int32_t* status) {
 }
 
 // Largest events first (by clusters, log2 buckets): a coarse LPT order for the
-// work-stealing finder.  Single workgroup; the order inside a bucket is
-// whatever the atomics give -- results never depend on it.
-__global__ __launch_bounds__(1024) void k_order(Work w, int n_events, const int32_t* clu_off) {
-    __shared__ int hist[33];
-    __shared__ int start[33];
-    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
+// work-stealing finder, in two lists -- events whose planes all fit kp (the
+// first LDS tile) into w.order, the others into `big`.  Single workgroup; the
+// order inside a bucket is whatever the atomics give -- results never depend
+// on it.
+__global__ __launch_bounds__(1024) void k_order(Work w, int n_events, const int32_t* clu_off, int kp, int32_t* big,
+                                                int big_count) {
+    __shared__ int hist[2][33];
+    __shared__ int start[2][33];
+    if (threadIdx.x < 66) (&hist[0][0])[threadIdx.x] = 0;
     __syncthreads();
+    // size class (log2 of the event's clusters) and whether a plane exceeds kp
+    auto classify = [&](int e, int* b) {
+        const int32_t* o = clu_off + e * kPlanes;
+        const int n = o[kPlanes] - o[0];
+        *b = 31 - (n > 0 ? 32 - __clz(n) : 0);
+        int over = 0;
+        for (int k = 0; k < kPlanes; ++k) over |= (o[k + 1] - o[k]) > kp;
+        return over;
+    };
     for (int e = threadIdx.x; e < n_events; e += blockDim.x) {
-        const int n = clu_off[(e + 1) * kPlanes] - clu_off[e * kPlanes];
-        const int b = n > 0 ? 32 - __clz(n) : 0;  // 0..31
-        atomicAdd(&hist[31 - b], 1);
+        int b;
+        const int g = classify(e, &b);
+        atomicAdd(&hist[g][b], 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 2) {
         int s = 0;
-        for (int b = 0; b < 33; ++b) { start[b] = s; s += hist[b]; }
+        for (int b = 0; b < 33; ++b) { start[threadIdx.x][b] = s; s += hist[threadIdx.x][b]; }
+        // k_reset cleared the counters: events for the first tile, and the
+        // head of the list the larger ones go to
+        w.counters[threadIdx.x == 0 ? 6 : big_count] = s;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n_events; e += blockDim.x) {
-        const int n = clu_off[(e + 1) * kPlanes] - clu_off[e * kPlanes];
-        const int b = n > 0 ? 32 - __clz(n) : 0;
-        w.order[atomicAdd(&start[31 - b], 1)] = e;
+        int b;
+        if (classify(e, &b)) big[atomicAdd(&start[1][b], 1)] = e;
+        else w.order[atomicAdd(&start[0][b], 1)] = e;
     }
 }
 
@@ -177,8 +192,9 @@ hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, w, n_events, clu_off);
+hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, int kp, int32_t* big, int big_count,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, w, n_events, clu_off, kp, big, big_count);
     return hipGetLastError();
 }
 

@@ -111,15 +111,20 @@ struct DecodeArgs {
 
 // launchers (return hipError_t)
 hipError_t launch_reset(const Work& w, int n_events, int32_t* status, hipStream_t s);
-hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, hipStream_t s);
+hipError_t launch_order(const Work& w, int n_events, const int32_t* clu_off, int kp, int32_t* big, int big_count,
+                        hipStream_t s);
 hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-// The finder in two enqueues: the LDS-tile pass of the configured tile over all
-// events (grid0 workgroups, persistent); then a second LDS pass with the next
-// larger tile over the events that did not fit (tiles 0 and 1; grid1), and the
-// global-memory finder over what is left.
-hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid0, hipStream_t s);
-hipError_t launch_finder_rest(FindArgs a, int threads, int tile, int grid1, hipStream_t s);
+// The finder's three passes over the lists k_order made: the configured LDS
+// tile over the events that fit it (w.order); the next larger tile (512
+// threads per event) over those that did not (w.large; tiles 0 and 1); the
+// global-memory finder over what neither took (w.large2).  Plane capacity of
+// each tile: tile_planes.
+int tile_planes(int tile);
+hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid, hipStream_t s);
+hipError_t launch_finder_second(FindArgs a, int tile, int grid, hipStream_t s);
+hipError_t launch_finder_large(FindArgs a, hipStream_t s);
+constexpr int kSecondPassThreads = 512;
 hipError_t launch_accept(const FindArgs& a, hipStream_t s);
 hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);

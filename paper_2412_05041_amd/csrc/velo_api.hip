@@ -195,15 +195,29 @@ int grid_for(velo_ctx* c, int n_events, int threads, int tile) {
     return std::max(1, std::min(n_events, g));
 }
 
-// The second LDS pass gets the events too large for the first tile: the
-// heaviest of the batch, few of them, so it always runs 512 threads per event.
-constexpr int kSecondPassThreads = 512;
+int mark(velo_ctx* c, int i, hipStream_t s, bool on);
 
-hipError_t enqueue_finder(velo_ctx* c, const FindArgs& fa, int E, hipStream_t s) {
-    const hipError_t e = launch_finder_first(fa, c->threads, c->tile, grid_for(c, E, c->threads, c->tile), s);
-    return e != hipSuccess ? e
-                           : launch_finder_rest(fa, kSecondPassThreads, c->tile,
-                                                grid_for(c, E, kSecondPassThreads, c->tile + 1), s);
+// Event lists for the finder (k_order): events whose planes all fit the
+// configured tile, and the others -- for the next larger tile, or (tile 2)
+// straight for the global-memory finder.
+hipError_t enqueue_order(velo_ctx* c, int E, const int32_t* clu_off, hipStream_t s) {
+    return launch_order(c->w, E, clu_off, tile_planes(c->tile), c->tile < 2 ? c->w.large : c->w.large2,
+                        c->tile < 2 ? 2 : 5, s);
+}
+
+// The finder's passes, in order on the stream: the configured tile, then (tiles
+// 0 and 1) the next larger tile over the few events too large for it -- the
+// heaviest of the batch, 512 threads each -- then the global-memory finder.
+// (Running the second pass beside the first, on a stream of its own, shortens
+// one batch but slows batches in flight together: its 81 KB workgroups take the
+// LDS the first pass's smaller ones would use.)
+int enqueue_finder(velo_ctx* c, const FindArgs& fa, int E, hipStream_t s, bool timed) {
+    HIP_OK(launch_finder_first(fa, c->threads, c->tile, grid_for(c, E, c->threads, c->tile), s));
+    if (int rc = mark(c, 4, s, timed)) return rc;
+    if (c->tile < 2)
+        HIP_OK(launch_finder_second(fa, c->tile + 1, grid_for(c, E, kSecondPassThreads, c->tile + 1), s));
+    HIP_OK(launch_finder_large(fa, s));
+    return mark(c, 5, s, timed);
 }
 
 // Enqueue the finder (staging must be in place) and the output compaction.
@@ -217,7 +231,7 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
                      int32_t* trk_off, int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes,
                      uint8_t* trk_flags, float* trk_logit, float* par, int64_t trk_cap, int64_t hit_cap,
                      int32_t emit, int32_t* status, int64_t clu_limit, hipStream_t s, bool timed = false) {
-    HIP_OK(launch_order(c->w, E, clu_off, s));
+    HIP_OK(enqueue_order(c, E, clu_off, s));
     if (int rc = mark(c, 3, s, timed)) return rc;
     FindArgs fa{};
     fa.n_events = E;
@@ -235,10 +249,7 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     fa.seed_hits = c->seed_hits;
     fa.seed_cap = c->seed_cap;
     fa.seed_count = c->seed_count;
-    HIP_OK(launch_finder_first(fa, c->threads, c->tile, grid_for(c, E, c->threads, c->tile), s));
-    if (int rc = mark(c, 4, s, timed)) return rc;
-    HIP_OK(launch_finder_rest(fa, kSecondPassThreads, c->tile, grid_for(c, E, kSecondPassThreads, c->tile + 1), s));
-    if (int rc = mark(c, 5, s, timed)) return rc;
+    if (int rc = enqueue_finder(c, fa, E, s, timed)) return rc;
     HIP_OK(launch_accept(fa, s));
     if (c->p.mode == 1) HIP_OK(launch_mlp_accept(c->mlp, fa, s));
     if (int rc = mark(c, 6, s, timed)) return rc;
@@ -639,9 +650,9 @@ int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* c
             float tot = 0.0f;
             for (int r = 0; r <= reps; ++r) {
                 HIP_OK(launch_reset(c->w, E, nullptr, s));
-                HIP_OK(launch_order(c->w, E, clu_off, s));
+                HIP_OK(enqueue_order(c, E, clu_off, s));
                 HIP_OK(hipEventRecord(e0, s));
-                HIP_OK(enqueue_finder(c, fa, E, s));
+                if (int rc = enqueue_finder(c, fa, E, s, false)) return rc;
                 HIP_OK(hipEventRecord(e1, s));
                 HIP_OK(hipEventSynchronize(e1));
                 float ms = 0.0f;
