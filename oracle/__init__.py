@@ -196,6 +196,19 @@ def kalman(trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, plane_z, sigma, ms, f
     return out[:T]
 
 
+def extrapolate(par, x_hit, z_mag, z_t, kick, p_min):
+    """VELO states par[n][8] (x, y, z, tx, ty, ...) through a single-kink magnet:
+    [n, 8] = x, y at z_mag; x (straight) and y at z_t; x window low, high for
+    p >= p_min; q/p leading to x_hit (0 if x_hit is None); slope after the kink."""
+    par = np.ascontiguousarray(par, np.float32).reshape(-1, 8)
+    n = par.shape[0]
+    xh = None if x_hit is None else np.ascontiguousarray(x_hit, np.float32)
+    out = np.zeros((max(n, 1), 8), np.float64)
+    lib().vo_extrapolate(C.c_longlong(n), _p(par), _p(xh), C.c_double(z_mag), C.c_double(z_t),
+                         C.c_double(kick), C.c_double(p_min), _p(out))
+    return out[:n]
+
+
 def decode(bank_off, bank, n_events, pix_cap=None):
     """Super-pixel banks -> (pix_off [E*26+1], pix_id sorted per plane, event flags, total)."""
     bank_off = np.ascontiguousarray(bank_off, np.int32)

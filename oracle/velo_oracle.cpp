@@ -798,6 +798,38 @@ long long vo_find_tracks(int n_events, const int32_t* clu_off, const float* clu_
     return T;
 }
 
+// Forward extrapolation of VELO states through the magnet (the first step of
+// forward tracking in section "HLT1 details and results": a straight line from
+// the VELO to the middle of the magnet, the field replaced by a single change
+// of slope there, proportional to charge / momentum).  FP64 closed form.
+// par[t*8 + {0..4}] = x, y, z, tx, ty of the VELO state (the fit's output);
+// x_hit (nullable) = x of a hit at z_t.  out[t*8 + {0..7}] = x, y at z_mag;
+// x of the straight line and y at z_t; the x window at z_t holding every track
+// with momentum >= p_min (x_lin -+ kick / p_min * (z_t - z_mag)); the q/p that
+// leads to x_hit (0 without hits); the slope after the kink for that q/p.
+void vo_extrapolate(long long n, const float* par, const float* x_hit, double z_mag, double z_t, double kick,
+                    double p_min, double* out) {
+    for (long long t = 0; t < n; ++t) {
+        const float* p = par + 8 * t;
+        const double x0 = p[0], y0 = p[1], z0 = p[2], tx = p[3], ty = p[4];
+        const double xm = x0 + tx * (z_mag - z0);
+        const double ym = y0 + ty * (z_mag - z0);
+        const double lever = z_t - z_mag;
+        const double xl = xm + tx * lever;
+        const double w = kick / p_min * lever;
+        const double qop = x_hit ? ((double(x_hit[t]) - xm) / lever - tx) / kick : 0.0;
+        double* o = out + 8 * t;
+        o[0] = xm;
+        o[1] = ym;
+        o[2] = xl;
+        o[3] = y0 + ty * (z_t - z0);
+        o[4] = xl - w;
+        o[5] = xl + w;
+        o[6] = qop;
+        o[7] = tx + kick * qop;
+    }
+}
+
 // Seed features of given triplets: hits[n][3] are global cluster indices on
 // planes k, k+1, k+2 of one event.  Returns 0, or -1 (nothing written past the
 // offending row) when a triplet is not on three consecutive planes of one event.
