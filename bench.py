@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# an illustrative magnet for --extrapolate (kink plane, tracker plane in mm; slope
+# change per unit q/p in rad GeV; smallest momentum of the window in GeV)
+MAGNET = dict(z_mag=5200.0, z_t=7800.0, kick=1.2, p_min=3.0)
 METRIC = "VELO events/s at nominal occupancy (1 GPU), eff/ghost rate; % HBM roofline"
 
 
@@ -118,6 +121,8 @@ def main():
     ap.add_argument("--launch", default=None, help="threads,tile of the finder (skips the autotuner)")
     ap.add_argument("--raw", action="store_true",
                     help="start each step from super-pixel raw banks: velo_decode, then the path")
+    ap.add_argument("--extrapolate", action="store_true",
+                    help="also run velo_extrapolate on each step's tracks (an illustrative single-kink magnet)")
     ap.add_argument("--kalman", type=float, default=None, metavar="MS",
                     help="also run velo_kalman_fit on each step's tracks (slope noise per plane, rad)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -199,10 +204,19 @@ def main():
             if args.kalman is not None:
                 self.kal_out = torch.empty((max(self.bufs["trk_cap"], 1), 16), dtype=torch.float32,
                                            device=ctx.device)
+            self.ext_out = None
+            if args.extrapolate:
+                self.ext_out = torch.empty((max(self.bufs["trk_cap"], 1), 8), dtype=torch.float32,
+                                           device=ctx.device)
             self.dec = None
             if bank is not None:
                 self.dec = ctx.decode(d_bank_off, d_bank, batch.n_pix)
                 self.dec_ids = self.dec["pix_id"][:batch.n_pix]
+
+        def extrapolate(self):
+            b = self.bufs
+            self.v.extrapolate(b["par"], MAGNET, max_tracks=b["trk_cap"], d_n_tracks=b["trk_off"][E:],
+                               out=self.ext_out)
 
         def kalman(self):
             b = self.bufs
@@ -217,6 +231,8 @@ def main():
             (self.v.pipeline if args.path == "fused" else self.v.three_call)(o, i, self.bufs)
             if self.kal_out is not None:
                 self.kalman()
+            if self.ext_out is not None:
+                self.extrapolate()
 
     lanes = [Lane(v)]
     th0, tl0 = v.get_launch()
@@ -278,6 +294,7 @@ def main():
     dec = lanes[0].dec
     kal_out = lanes[0].kal_out
     kalman = lanes[0].kalman
+    ext_out = lanes[0].ext_out
     st = v.read_status(bufs["status"])
     if args.path == "three-call":
         stc = v.read_status(bufs["status_clu"])
@@ -328,6 +345,20 @@ def main():
         kbytes = 12 * H + 72 * T  # hit index + x, y per hit; offset, planes, 16-float state per track
         kal = {"ms": kms, "alg_bytes": kbytes, "achieved_GBs": kbytes / (kms * 1e-3) / 1e9,
                "frac": kbytes / (kms * 1e-3) / (HBM_PEAK_GBS * 1e9), "ms_noise": args.kalman}
+    ext = None
+    if ext_out is not None:  # the extrapolation alone, HIP events on the stream it runs on
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lanes[0].extrapolate()
+        e0.record()
+        for _ in range(args.steps):
+            lanes[0].extrapolate()
+        e1.record()
+        torch.cuda.synchronize()
+        ems = e0.elapsed_time(e1) / args.steps
+        stages["extrapolate"] = ems
+        ebytes = 52 * T  # x, y, z, tx, ty in; 8 floats out per track
+        ext = {"ms": ems, "alg_bytes": ebytes, "achieved_GBs": ebytes / (ems * 1e-3) / 1e9,
+               "frac": ebytes / (ems * 1e-3) / (HBM_PEAK_GBS * 1e9), "magnet": MAGNET}
     # dominant kernel: the largest share of the batch's device time -- its
     # duration, for the finder passes weighted by the fraction of the events
     # they process (the second pass takes a few hundred workgroups, not the GPU)
@@ -382,6 +413,7 @@ def main():
             "seed_filter": bool(args.seed_filter),
             "path": args.path,
             "kalman_ms": args.kalman,
+            "extrapolate": bool(args.extrapolate),
             "raw_banks": bool(args.raw),
             "launch": {"threads_per_event": th, "tile": tl},
             "autotune_ms": tune_ms,
@@ -407,6 +439,7 @@ def main():
         "stages_ms": stages,
         "events_second_tile_or_large": int(ev_rest.sum()),
         "kalman": kal,
+        "extrapolate": ext,
         "cpu_baseline": cpu,
     }
     if args.calib_copy_mib > 0:

@@ -260,6 +260,27 @@ int velo_mlp_set_adam(velo_ctx* ctx, float beta1, float beta2, float eps);
 int velo_mlp_get_state(velo_ctx* ctx, float* h_master, float* h_m, float* h_v, int64_t* h_step);
 int velo_mlp_set_state(velo_ctx* ctx, const float* h_master, const float* h_m, const float* h_v, int64_t step);
 
+/* Forward extrapolation of VELO states through the magnet -- the first step of
+ * forward tracking (section "HLT1 details and results": straight from the
+ * VELO to the middle of the magnet, the field replaced there by one change of
+ * slope that depends on the track's momentum).  The magnet is the caller's:
+ *   z_mag: the plane of the kink (mm); z_t: the tracker plane (mm), > z_mag;
+ *   kick: change of the x slope per unit charge / momentum (rad GeV), != 0;
+ *   p_min: the smallest momentum the window must hold (GeV), > 0.
+ * d_par: [max_tracks][8] states as velo_fit writes them (x, y, z, tx, ty at
+ * z; the other three are not read); d_x_hit (nullable): [max_tracks] x of a
+ * hit at z_t; d_n_tracks (nullable): device count of tracks, as for velo_fit.
+ * d_out: [max_tracks][8] = x, y at z_mag; x of the straight line and y at z_t
+ * (no kink in y); x_lo, x_hi = the straight x -+ kick / p_min * (z_t - z_mag);
+ * the q/p that takes the track to x_hit (0 without d_x_hit); tx after the kink
+ * for that q/p.  FP32.  d_par and d_out 16-byte aligned.
+ * Errors: VELO_ERR_ARG for null arrays, misaligned rows or an invalid magnet. */
+typedef struct velo_magnet {
+    float z_mag, z_t, kick, p_min;
+} velo_magnet;
+int velo_extrapolate(velo_ctx* ctx, int64_t max_tracks, const int32_t* d_n_tracks, const float* d_par,
+                     const float* d_x_hit, const velo_magnet* magnet, float* d_out, void* stream);
+
 /* Seed-level learned filter (a triplet filter: an extension of the simplified
  * pattern recognition that the first trigger stage uses for throughput --
  * section "HLT1 details and results" -- with the track filter's network

@@ -53,6 +53,16 @@ struct FindArgs {
     unsigned long long* seed_count;  // candidates seen (may exceed seed_cap)
 };
 
+// Forward extrapolation through a single-kink magnet (velo_extrapolate).
+struct ExtrapArgs {
+    int64_t max_tracks;
+    const int32_t* n_tracks;  // device count (nullable: max_tracks)
+    const float* par;         // [max_tracks][8] VELO states (x, y, z, tx, ty, ...), 16-byte aligned
+    const float* x_hit;       // [max_tracks] x of a hit at z_t (nullable)
+    float z_mag, z_t, kick, p_min;
+    float* out;               // [max_tracks][8], 16-byte aligned
+};
+
 struct OutArgs {
     int n_events;
     const int32_t* clu_off;
@@ -129,6 +139,7 @@ hipError_t launch_accept(const FindArgs& a, hipStream_t s);
 hipError_t launch_scan(const OutArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, hipStream_t s);
+hipError_t launch_extrapolate(const ExtrapArgs& a, hipStream_t s);
 hipError_t launch_kalman(const KalmanArgs& a, hipStream_t s);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s);
 

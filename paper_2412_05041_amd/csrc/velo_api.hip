@@ -525,6 +525,32 @@ int velo_kalman_fit(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, co
     return VELO_OK;
 }
 
+int velo_extrapolate(velo_ctx* c, int64_t max_tracks, const int32_t* n_tracks, const float* par, const float* x_hit,
+                     const velo_magnet* m, float* out, void* stream) {
+    if (!c || !m) return fail(VELO_ERR_ARG, "null argument");
+    if (max_tracks < 0) return fail(VELO_ERR_ARG, "max_tracks < 0");
+    if (!std::isfinite(m->z_mag) || !std::isfinite(m->z_t) || !(m->z_t > m->z_mag))
+        return fail(VELO_ERR_ARG, "need finite z_mag < z_t");
+    if (!std::isfinite(m->kick) || m->kick == 0.0f) return fail(VELO_ERR_ARG, "kick must be finite and non-zero");
+    if (!std::isfinite(m->p_min) || !(m->p_min > 0.0f)) return fail(VELO_ERR_ARG, "p_min must be finite and > 0");
+    if (max_tracks == 0) return VELO_OK;
+    if (!par || !out) return fail(VELO_ERR_ARG, "null argument");
+    if ((reinterpret_cast<uintptr_t>(par) | reinterpret_cast<uintptr_t>(out)) & 15)
+        return fail(VELO_ERR_ARG, "par and out rows must be 16-byte aligned");
+    ExtrapArgs a{};
+    a.max_tracks = max_tracks;
+    a.n_tracks = n_tracks;
+    a.par = par;
+    a.x_hit = x_hit;
+    a.z_mag = m->z_mag;
+    a.z_t = m->z_t;
+    a.kick = m->kick;
+    a.p_min = m->p_min;
+    a.out = out;
+    HIP_OK(launch_extrapolate(a, (hipStream_t)stream));
+    return VELO_OK;
+}
+
 int velo_pipeline(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t* pix_id, int32_t* pix_clu,
                   int32_t* clu_off, float* clu_x, float* clu_y, int64_t clu_cap, int32_t* trk_off,
                   int32_t* trk_hit_off, int32_t* trk_hit, uint32_t* trk_planes, uint8_t* trk_flags,

@@ -56,6 +56,8 @@ _SIGS = {
                       C.c_void_p],
     "velo_mlp_set_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_seed_filter_set": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float],
+    "velo_extrapolate": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_void_p],
     "velo_seed_emit": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "velo_mlp_get_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_features": [C.c_void_p, C.c_int64] + [C.c_void_p] * 8,
@@ -73,6 +75,10 @@ _SIGS = {
     "velo_status_string": [C.c_int],
     "velo_last_error": [],
 }
+
+
+class _Magnet(C.Structure):
+    _fields_ = [("z_mag", C.c_float), ("z_t", C.c_float), ("kick", C.c_float), ("p_min", C.c_float)]
 
 
 def lib():
@@ -218,6 +224,18 @@ class Velo:
                        status=self.status_buffer(E))
         _check(lib().velo_decode(self.h, E, _ptr(bank_off), _ptr(bank), _ptr(out["pix_off"]), _ptr(out["pix_id"]),
                                  int(pix_cap), _ptr(out["status"]), _stream()))
+        return out
+
+    def extrapolate(self, par, magnet: dict, x_hit=None, n_tracks=None, max_tracks=None, d_n_tracks=None, out=None):
+        """VELO states par[n][8] through a single-kink magnet (z_mag, z_t, kick,
+        p_min): [n][8] = x, y at z_mag; x, y at z_t; x window; q/p to x_hit;
+        slope after the kink."""
+        n = int(max_tracks if max_tracks is not None else (n_tracks if n_tracks is not None else par.shape[0]))
+        if out is None:
+            out = torch.empty((max(n, 1), 8), dtype=torch.float32, device=self.device)
+        m = _Magnet(magnet["z_mag"], magnet["z_t"], magnet["kick"], magnet["p_min"])
+        _check(lib().velo_extrapolate(self.h, n, _ptr(d_n_tracks), _ptr(par), _ptr(x_hit), C.byref(m), _ptr(out),
+                                      _stream()))
         return out
 
     def kalman_fit(self, trk_hit_off, trk_hit, trk_planes, clu_x, clu_y, ms, n_tracks=None, max_tracks=None,
