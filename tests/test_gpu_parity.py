@@ -154,13 +154,22 @@ def test_every_launch_configuration_gives_identical_tracks(velo_mod, threads, ti
         assert np.any(st[8:8 + b.n_events] & velo_mod.EV_SECOND_TILE)
 
 
-def test_large_event_path_on_dense_events(velo_mod):
-    say("[parity] dense events (large path)")
+@pytest.fixture(scope="module")
+def dense():
     w = gen.Workload("dense", 2, 4321, "uniform", trk_lo=1500, trk_hi=2500, ms_sigma=1e-3, noise_p=5e-4)
     b = gen.generate(w)
     cut = cuts("ms")
     c, t = oracle_run(b, cut)
+    return b, cut, c, t
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_large_event_path_on_dense_events(velo_mod, dense, tile):
+    # tile 1: the second LDS pass refuses them too; tile 2: straight to global memory
+    say(f"[parity] dense events (large path), tile {tile}")
+    b, cut, c, t = dense
     v = velo_mod.Velo(b.plane_z, cut)
+    v.set_launch(512, tile)
     v.reserve(b.n_events, b.n_pix, b.n_pix)
     off, ids = velo_mod.to_device(b)
     bufs = v.pipeline_buffers(b.n_events, b.n_pix)
