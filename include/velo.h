@@ -211,7 +211,9 @@ int velo_set_timing(velo_ctx* ctx, int32_t on);
 int velo_last_timing(velo_ctx* ctx, float* h_ms, int32_t n);
 
 /* Launch configuration of the track finder: threads per event (64, 128, 256, 512)
- * and LDS tile (0 small, 1 medium, 2 large).  Outputs never depend on it. */
+ * and LDS tile (plane capacity 0: 256, 1: 512, 2: 1024 clusters; events with a
+ * larger plane go on to the next tile, then to global memory).  Outputs never
+ * depend on it. */
 int velo_set_launch(velo_ctx* ctx, int32_t threads, int32_t tile);
 int velo_get_launch(velo_ctx* ctx, int32_t* threads, int32_t* tile);
 

@@ -1450,8 +1450,10 @@ hipError_t launch_finder_first(FindArgs a, int threads, int tile, int grid, hipS
     a.q_in = a.w.order;
     a.q_count = 6;
     a.q_cursor = 1;
-    a.q_out = a.w.large2;
-    a.q_out_count = 5;
+    // events that overflow the tile's track or candidate capacity join the
+    // second pass's list (it starts after this pass), or go to global memory
+    a.q_out = tile < 2 ? a.w.large : a.w.large2;
+    a.q_out_count = tile < 2 ? 2 : 5;
     return launch_find_lds(a, threads, tile, grid, s);
 }
 

@@ -127,7 +127,8 @@ hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 // The finder's three passes over the lists k_order made: the configured LDS
 // tile over the events that fit it (w.order); the next larger tile (512
-// threads per event) over those that did not (w.large; tiles 0 and 1); the
+// threads per event) over those that did not, and over those that overflowed
+// the first tile's track or candidate capacity (w.large; tiles 0 and 1); the
 // global-memory finder over what neither took (w.large2).  Plane capacity of
 // each tile: tile_planes.
 int tile_planes(int tile);
