@@ -16,7 +16,13 @@
  *   velo_pipeline     the three steps in one stream-ordered call (persistent
  *                     work-stealing kernels, captured once in a HIP graph);
  *   velo_mlp_*        the learned ghost filter (10 -> 32 -> 32 -> 1, BF16 MFMA,
- *                     FP32 accumulation) and its on-GPU training step.
+ *                     FP32 accumulation) and its on-GPU training step;
+ *   velo_seed_*       a learned seed (triplet) filter inside the finder, and the
+ *                     emission of seed candidates to train it;
+ *   velo_kalman_fit, velo_decode, velo_extrapolate
+ *                     a parameterised Kalman fit of the VELO segment, a raw-bank
+ *                     decode front end, and the extrapolation through a
+ *                     single-kink magnet that forward tracking starts from.
  *
  * Conventions
  *   - Every d_* argument is a DEVICE pointer owned by the caller; it must stay
@@ -307,8 +313,8 @@ int velo_seed_filter_set(velo_ctx* ctx, const float* h_weights, const float* h_n
  * its ten raw features to d_feat [cap][10] (FP32) and its three global cluster
  * indices (planes k, k+1, k+2) to d_hits [cap][3]; *d_count (caller-zeroed
  * device counter) counts all of them, also those beyond `cap`, which are not
- * written.  Order is unspecified, and an event that the LDS-tile finder hands
- * on to the large-event finder may emit some candidates twice.  All NULL
+ * written.  Order is unspecified, and an event that one finder pass hands on
+ * to the next (a capacity it overflowed) may emit some candidates twice.  All NULL
  * switches emission off.  The buffers are caller-owned and must stay valid
  * while emission is on. */
 int velo_seed_emit(velo_ctx* ctx, float* d_feat, int32_t* d_hits, int64_t cap, unsigned long long* d_count);
