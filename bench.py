@@ -5,9 +5,10 @@ Workload (the nominal-occupancy configuration): 1000 synthetic events, Poisson(5
 primary vertices x Poisson(40) tracks, 1 mrad scattering per plane, calibrated
 noise giving ~3k clusters per event (seed 1002).  One step = the whole path
 (clustering + staging, track finding, acceptance, CSR output, fit) over the
-batch, inputs resident in HBM, launched as one replayed HIP graph; by default three batches are in flight, each
-on its own context, buffers and HIP stream (--streams), so that one batch's
-clustering and output overlap the tail of another's track finding.
+batch, inputs resident in HBM, launched as one replayed HIP graph; by default four batches are in flight (one
+per hardware queue of the process), each on its own context, buffers and HIP
+stream (--streams), so that one batch's clustering and output overlap the tail
+of another's track finding.
 
 Prints ONE JSON line: events/s, the dominant kernel's HBM roofline fraction
 (algorithmic bytes / its HIP-event-timed duration), efficiency / ghost rate of
@@ -106,7 +107,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["plain", "learned"], default="plain")
-    ap.add_argument("--streams", type=int, default=3,
+    ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: each on its own context, buffers and HIP stream")
     ap.add_argument("--seed-filter", action="store_true",
                     help="seed-level learned filter with the committed network (configs/seed_default.npz)")
