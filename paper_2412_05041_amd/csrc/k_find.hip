@@ -150,9 +150,10 @@ struct LdsStore {
     // enumeration scratch (seeding slots are free before the claiming rounds)
     __device__ int32_t* pref() { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
     __device__ int32_t* ebuf() { return reinterpret_cast<int32_t*>(&t->slota[0][0]); }
-    // seed-filter broadcast scratch, 2 kT floats (the seeding slots, still free)
+    // seed-filter broadcast scratch: 2 x 32 floats for each of a round's (at
+    // most 16) candidate groups, in the seeding slots (still free then)
     __device__ float* bcast() { return reinterpret_cast<float*>(&t->slota[0][0]); }
-    static_assert(sizeof(uint64_t) * 3 * kP >= sizeof(float) * 2 * kT, "broadcast scratch fits the slots");
+    static_assert(sizeof(uint64_t) * 3 * kP >= sizeof(float) * 2 * 16 * kSeedH, "broadcast scratch fits the slots");
     __device__ uint32_t& tmask(int i) { return t->tmask[i]; }
     __device__ int16_t& twant(int i) { return t->twant[i]; }
     __device__ float& cq(int i) { return t->cq[i]; }
@@ -182,7 +183,7 @@ struct GlobalStore {
     int seed_k = 0;  // plane of h0 during seeding
     const float* seedw = nullptr;  // seed network in LDS, rows [unit][input] (seed variant)
     float* seedh = nullptr;        // per-thread first-layer activations in LDS, [unit][thread]
-    __device__ float* bcast() { return seedh; }  // seed-filter broadcast scratch (>= 2 kT floats)
+    __device__ float* bcast() { return seedh; }  // seed-filter broadcast scratch (>= 2 x 16 x 32 floats)
     __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
     __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
     __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
@@ -1056,8 +1057,9 @@ __device__ __forceinline__ void seed_features(S& st, const Params& p, int k, int
 // The network evaluates in FP32 in one fixed order: features standardised as
 // (f - mean) * (1 / sd), each unit starts from its bias and adds weight x input
 // for inputs in ascending order, ReLU between layers.  Two layouts of the same
-// arithmetic: a half-wave per candidate (lane o holds hidden unit o, its
-// outputs broadcast to the half-wave through LDS), and -- in the large-event finder, whose
+// arithmetic: a group of lanes per candidate (each lane holds one or two
+// hidden units, their outputs broadcast to the group through LDS), and -- in
+// the large-event finder, whose
 // crowded plane steps bring thousands of candidates -- one candidate per lane
 // with the weights read from an LDS copy as uniform operands.  A candidate
 // whose logit exceeds the threshold dies.
@@ -1112,20 +1114,26 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __rest
             }
         }
     } else {
-        const int o = threadIdx.x & (kSeedH - 1);
-        constexpr int kGroups = kT / kSeedH;
-        static_assert(kWave == 2 * kSeedH, "two candidates per wave");
-        // this half-wave's 32 activations of each layer, broadcast through LDS
-        float* b1 = st.bcast() + (threadIdx.x / kSeedH) * kSeedH;
-        float* b2 = b1 + kT;
+        // a group of kL lanes per candidate, kU hidden units per lane: half
+        // a wave (one unit each) for 512-thread workgroups, a quarter (two
+        // each) for smaller ones, so that a round always takes 16 candidates
+        constexpr int kL = kT >= 512 ? kSeedH : kSeedH / 2;
+        constexpr int kU = kSeedH / kL;
+        constexpr int kGroups = kT / kL;
+        static_assert(kWave % kL == 0, "a candidate's lanes lie in one wave");
+        static_assert(kGroups <= 16, "the broadcast scratch holds 16 groups");
+        const int l = threadIdx.x & (kL - 1);
+        // this group's 32 activations of each layer, broadcast through LDS
+        float* b1 = st.bcast() + (threadIdx.x / kL) * kSeedH;
+        float* b2 = b1 + kGroups * kSeedH;
         for (int c0 = 0; c0 < nc; c0 += kGroups) {
-            const int c = c0 + (int)threadIdx.x / kSeedH;
+            const int c = c0 + (int)threadIdx.x / kL;
             const bool valid = c < nc;
-            // idle half-waves take a valid candidate and still join the broadcasts
+            // idle groups take a valid candidate and still join the broadcasts
             float f[kSeedIn];
             int i0, i1, i2;
             seed_features(st, p, k, valid ? c : nc - 1, fn, f, &i0, &i1, &i2);
-            if (a.seed_feat && valid && o == 0) emit(f, i0, i1, i2);
+            if (a.seed_feat && valid && l == 0) emit(f, i0, i1, i2);
             if (!on) continue;
             // the per-lane weight rows are re-read each round (L1) rather than
             // held in registers across the loop; the uniform ones come
@@ -1134,20 +1142,26 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __rest
             asm volatile("" : "+s"(Wl));
             typedef const __attribute__((address_space(1))) float* gptr;
             const gptr Wg = (gptr)Wl;
-            float h = Wg[kSeedB1 + o];
-            for (int i = 0; i < kSeedIn; ++i) {
-                const float xs = (f[i] - W[kSeedNorm + i]) * W[kSeedNorm + kSeedIn + i];
-                h = h + Wg[kSeedW1T + i * kSeedH + o] * xs;
+            float xs[kSeedIn];
+            for (int i = 0; i < kSeedIn; ++i) xs[i] = (f[i] - W[kSeedNorm + i]) * W[kSeedNorm + kSeedIn + i];
+            for (int u = 0; u < kU; ++u) {  // units l * kU + u
+                const int o = l * kU + u;
+                float h = Wg[kSeedB1 + o];
+                for (int i = 0; i < kSeedIn; ++i) h = h + Wg[kSeedW1T + i * kSeedH + o] * xs[i];
+                b1[o] = h > 0.0f ? h : 0.0f;
             }
-            b1[o] = h > 0.0f ? h : 0.0f;
             group_sync<kWave, kT>();
-            h = Wg[kSeedB2 + o];
-            for (int i = 0; i < kSeedH; ++i) h = h + Wg[kSeedW2T + i * kSeedH + o] * b1[i];
-            b2[o] = h > 0.0f ? h : 0.0f;
+            float h2[kU];
+            for (int u = 0; u < kU; ++u) h2[u] = Wg[kSeedB2 + l * kU + u];
+            for (int i = 0; i < kSeedH; ++i) {
+                const float x = b1[i];
+                for (int u = 0; u < kU; ++u) h2[u] = h2[u] + Wg[kSeedW2T + i * kSeedH + l * kU + u] * x;
+            }
+            for (int u = 0; u < kU; ++u) b2[l * kU + u] = h2[u] > 0.0f ? h2[u] : 0.0f;
             group_sync<kWave, kT>();
             float z = W[kSeedB3];
             for (int i = 0; i < kSeedH; ++i) z = z + W[kSeedW3 + i] * b2[i];
-            if (valid && o == 0 && z > W[kSeedThr]) st.calive(c) = 0;
+            if (valid && l == 0 && z > W[kSeedThr]) st.calive(c) = 0;
             group_sync<kWave, kT>();  // the next round rewrites b1 and b2
         }
     }
