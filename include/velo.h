@@ -224,7 +224,11 @@ int velo_set_launch(velo_ctx* ctx, int32_t threads, int32_t tile);
 int velo_get_launch(velo_ctx* ctx, int32_t* threads, int32_t* tile);
 
 /* Times every launch configuration on the given clusters (device inputs, as
- * for velo_find_tracks) and keeps the fastest.  Synchronises the stream.
+ * for velo_find_tracks) and keeps the fastest.  Synchronises the stream.  It
+ * times one batch at a time; a caller that keeps several batches in flight
+ * (one context and stream each) may find another launch faster -- a small
+ * first tile, whose second pass overlaps the other batches -- and should time
+ * the candidates that way (bench.py does).
  * h_ms (nullable) receives VELO_N_LAUNCH timings, threads-major (64, 128,
  * 256, 512) then tile. */
 #define VELO_N_LAUNCH 12
