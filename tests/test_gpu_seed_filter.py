@@ -5,7 +5,9 @@ candidates of every step, with the oracle's FP32 features; with a network
 switched on, the tracks (CSR hit lists, plane masks, flags) equal the oracle's
 run with the same network, on the LDS-tile path (every launch configuration),
 the large-event path and the graph-captured pipeline, and switching the filter
-off and on again gives the plain and the filtered oracle results in turn.
+off and on again gives the plain and the filtered oracle results in turn.  With
+the learned track filter on as well, the candidates stay bit-exact and the
+acceptance decisions agree away from the band edge.
 
 The network is a fixed He-uniform draw with fixed feature scales; its
 threshold is the 70 % quantile of the oracle's own logits on the oracle's
@@ -158,3 +160,37 @@ def test_pipeline_switches_the_filter(velo_mod):
         torch.cuda.synchronize()
         assert v.read_status(bufs["status"])[0] == 0
         assert_tracks_equal(bufs, ref, check_flags=True)
+
+
+def test_seed_filter_with_the_learned_acceptance(velo_mod):
+    """Both networks at once: the seed filter decides which candidates exist
+    (bit-exact), the BF16 track network then decides acceptance (logits within
+    the track network's tolerance, decisions equal away from the band edge)."""
+    b = make("nominal", 40, 51)
+    cut = dict(cuts("ms"), mode=1, logit_band=0.1)
+    c = oracle.cluster(b.pix_off, b.pix_id)
+    seed = network(c, b.plane_z, cuts("ms"))
+    rng = np.random.default_rng(52)
+    master = rng.normal(0, 0.5, 1441).astype(np.float32)
+    norm = np.concatenate([[50, 8, 0, 0, 5, 5, 5, 5, 0.6, 0.8],
+                           [100, 4, 0.1, 0.1, 5, 5, 10, 10, 0.2, 0.2]]).astype(np.float32)
+    t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], b.plane_z, cut, mlp=(master, norm),
+                           emit_rejected=True, seed=seed)
+    assert t["stats"][3] > 0
+    v = velo_mod.Velo(b.plane_z, cut)
+    v.mlp_set_weights(master, norm)
+    v.seed_filter_set(*seed)
+    v.reserve(b.n_events, b.n_pix, b.n_pix)
+    off, ids = velo_mod.to_device(b)
+    gc = v.cluster(off, ids)
+    gt = v.find_tracks(gc["clu_off"], gc["clu_x"], gc["clu_y"], emit_rejected=True)
+    torch.cuda.synchronize()
+    T = len(t["trk_planes"])
+    H = int(t["trk_hit_off"][-1])
+    assert np.array_equal(np_(gt["trk_off"]), t["trk_off"])
+    assert np.array_equal(np_(gt["trk_hit"], H), t["trk_hit"])
+    assert np.array_equal(np_(gt["trk_planes"], T, np.uint32), t["trk_planes"])
+    z, zo = np_(gt["trk_logit"], T), t["trk_logit"]
+    assert np.all(np.abs(z - zo) <= 2e-2 * np.maximum(1.0, np.abs(zo)))
+    sure = np.abs(zo) > 0.1 + 2e-2
+    assert np.array_equal(np_(gt["trk_flags"], T)[sure] & 0x0f, t["trk_flags"][sure] & 0x0f)
