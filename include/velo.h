@@ -97,7 +97,8 @@ typedef struct velo_geometry {
 } velo_geometry;
 
 /* Cut set of the track finder.  All comparisons are FP32, evaluated in the
- * order documented in the design doc, with no fused multiply-add. */
+ * order their expressions are written in (the comments on each field give the
+ * quantity), with no fused multiply-add. */
 typedef struct velo_cuts {
     float t_max;      /* seed: |tx| <= t_max and |ty| <= t_max                     */
     float d2_max;     /* seed: squared closest approach of its line to the z axis  */

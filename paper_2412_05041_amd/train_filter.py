@@ -51,7 +51,7 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--test-events", type=int, default=5000)
     ap.add_argument("--out", default=learned.WEIGHTS)
-    ap.add_argument("--report", default="gpurun_out/learned_report.json")
+    ap.add_argument("--report", default="learned_report.json")
     args = ap.parse_args()
 
     loose = learned.cuts("loose")

@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--patience", type=int, default=5)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=seeds.WEIGHTS)
-    ap.add_argument("--report", default="gpurun_out/seed_report.json")
+    ap.add_argument("--report", default="seed_report.json")
     args = ap.parse_args()
 
     cut = learned.cuts("ms")

@@ -1,6 +1,6 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a
-message (this build has no multi-GPU path), and the help names every option
-the benchmark contract and the design doc's result table use."""
+message (the library has no multi-GPU path), and the help names every option
+the benchmark's documented runs use."""
 import os
 import subprocess
 import sys
