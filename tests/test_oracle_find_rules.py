@@ -23,7 +23,7 @@ import numpy as np
 import pytest
 
 import oracle
-from test_oracle_find import CUTS, ZS, as_input_positions, line_hits, run, tracks_of
+from test_oracle_find import CUTS, ZS, as_input_positions, event_from_hits, line_hits, run, tracks_of
 
 torch = pytest.importorskip("torch")
 
@@ -366,3 +366,114 @@ def test_rounded_gradient_uses_the_rounded_hidden_activation():
     sz = 1.0 / (1.0 + math.exp(-z))
     assert g[oW2] == pytest.approx(sz * z, rel=1e-14)
     assert g[oW3] == pytest.approx(sz * z, rel=1e-14)
+
+
+def test_rounded_gradient_uses_the_rounded_second_hidden_activation():
+    # the live path starts at the second layer: b2[0] = 1 + 2^-10 (its BF16
+    # rounding is 1.0 by the format), W3[0] = 1, everything else 0.  Forward:
+    # h2 = 1.0, z = 1; the straight-through gradient of W3[0] is
+    # sigmoid(1) * h2 = sigmoid(1), of b2[0] sigmoid(1).
+    w = np.zeros(1441, np.float32)
+    w[oB2] = np.float32(1.0 + 2.0 ** -10)
+    w[oW3] = 1.0
+    xb = np.zeros((1, 16), np.uint16)
+    loss, g = oracle.mlp_loss_grad(np.zeros(1, np.uint8), master=w, xb=xb, round_on=True)
+    sig = 1.0 / (1.0 + math.exp(-1.0))
+    assert loss == pytest.approx(math.log1p(math.exp(1.0)), rel=1e-14)
+    assert g[oW3] == pytest.approx(sig, rel=1e-14)
+    assert g[oB2] == pytest.approx(sig, rel=1e-14)
+    z = 1.0 + 2.0 ** -10
+    loss, g = oracle.mlp_loss_grad(np.zeros(1, np.uint8), master=w, xb=xb, round_on=False)
+    assert g[oW3] == pytest.approx(z / (1.0 + math.exp(-z)), rel=1e-14)
+
+
+@pytest.mark.parametrize("first", [+1.0, -1.0])
+def test_seed_tie_after_h0_breaks_on_h1(first):
+    # h0 and h2 in y = 0, so the prediction on plane k+1 has y = 0 exactly; two
+    # middle hits at the same x and y = +-d: bit-equal q with the same h0, so
+    # the lower h1 index takes the seed
+    k, d = 12, 0.2
+    x = lambda j: 15.0 + 0.04 * (Z[j] - Z[k])
+    hits = [(k, x(k), 0.0), (k + 1, x(k + 1), first * d), (k + 1, x(k + 1), -first * d), (k + 2, x(k + 2), 0.0)]
+    out, orig = run(hits, emit_rejected=True)
+    assert as_input_positions(out, orig) == [[0, 1, 3]]
+
+
+@pytest.mark.parametrize("first", [+1.0, -1.0])
+def test_seed_tie_after_h1_breaks_on_h2(first):
+    # h0 and h1 in y = 0; two last hits at the same x and y = +-d give slopes
+    # ty = +-d / dz2 (exact negatives) and so bit-equal middle misses with the
+    # same h0 and h1: the lower h2 index takes the seed
+    k, d = 12, 0.2
+    x = lambda j: 15.0 + 0.04 * (Z[j] - Z[k])
+    hits = [(k, x(k), 0.0), (k + 1, x(k + 1), 0.0), (k + 2, x(k + 2), first * d), (k + 2, x(k + 2), -first * d)]
+    out, orig = run(hits, emit_rejected=True)
+    assert as_input_positions(out, orig) == [[0, 1, 2]]
+
+
+# ------------------------------------------------- cuts are inclusive (<=)
+
+def test_middle_hit_cut_keeps_a_miss_equal_to_s_max():
+    # the candidate's own q (the finder's debug output) as the cut: kept; one
+    # ulp below: dropped
+    hits = line_hits((20.0, 0.0), (0.05, 0.0), [10, 11, 12], z0=Z[11])
+    hits[1] = (11, hits[1][1], hits[1][2] + 0.17)
+    out = run(hits, emit_rejected=True, dbg_event=0, dbg_step=10)[0]
+    assert len(out["dbg_cand"]) == 1
+    q = np.float32(out["dbg_cand"][0, 0])
+    assert len(tracks_of(run(hits, cuts=dict(CUTS, s_max=float(q)), emit_rejected=True)[0])) == 1
+    below = float(np.nextafter(q, np.float32(0)))
+    assert len(tracks_of(run(hits, cuts=dict(CUTS, s_max=below), emit_rejected=True)[0])) == 0
+
+
+def test_extension_cut_keeps_a_miss_equal_to_e_max():
+    # seed on planes 20-22, one hit on plane 19 off the line; its miss q from
+    # the prediction through the hits on 20 and 21, in FP32 as a line
+    # extrapolation: the cut at q keeps it, one ulp below drops it
+    hits = line_hits((20.0, 0.0), (0.05, 0.0), [20, 21, 22])
+    z = np.float32(Z)
+    x19 = 20.0 + 0.05 * (Z[19] - Z[20])
+    hits.append((19, x19, 0.33))
+    f = np.float32
+    (_, xa, ya), (_, xb, yb) = hits[1], hits[0]
+    tx = (f(xa) - f(xb)) / (z[21] - z[20])
+    ty = (f(ya) - f(yb)) / (z[21] - z[20])
+    ex = f(xb) + tx * (z[19] - z[20])
+    ey = f(yb) + ty * (z[19] - z[20])
+    dx, dy = f(x19) - ex, f(0.33) - ey
+    q = dx * dx + dy * dy
+    got = as_input_positions(*run(hits, cuts=dict(CUTS, e_max=float(q)), emit_rejected=True))
+    assert got == [[0, 1, 2, 3]]
+    below = float(np.nextafter(q, f(0)))
+    got = as_input_positions(*run(hits, cuts=dict(CUTS, e_max=below), emit_rejected=True))
+    assert got == [[0, 1, 2]]
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("t,found", [(0.39, True), (0.41, False)])
+def test_seed_slope_bound_applies_to_each_axis(axis, t, found):
+    # a radial line along x or along y; the other slope is 0
+    p = [0.0, 0.0]
+    p[axis] = 20.0
+    s = [0.0, 0.0]
+    s[axis] = t
+    out, _ = run(line_hits(tuple(p), tuple(s), [10, 11, 12], z0=Z[11]))
+    assert (len(tracks_of(out)) == 1) == found
+
+
+# ------------------------------------- seed feature: the closest-approach clip
+
+def test_seed_closest_approach_z_is_clipped_to_2000_mm():
+    # a radial line of slope 0.004 at radius 20 mm passes the axis 5000 mm
+    # upstream of its first plane: the feature reads -2000; with the slope
+    # reversed the line passes it 5000 mm downstream: +2000 (the features are
+    # defined for any triplet, the seed cuts aside); a line meeting the axis
+    # at z = -100 mm reads that z
+    def feat(x0, t):
+        hits = [(k, x0 + t * (Z[k] - Z[10]), 0.0) for k in (10, 11, 12)]
+        off, x, y, _ = event_from_hits(hits)
+        f = oracle.seed_features(np.array([[0, 1, 2]]), off, x, y, ZS)
+        return f[0]
+    assert feat(20.0, 0.004)[2] == np.float32(-2000.0)
+    assert feat(20.0, -0.004)[2] == np.float32(2000.0)
+    assert abs(feat(20.0, 20.0 / (Z[10] + 100.0))[2] - (-100.0)) < 1e-2

@@ -110,3 +110,16 @@ def test_adam_first_step_closed_form():
     oracle.adam(w, m, v, g, 1, lr=1e-3)
     # bias-corrected first step: w -= lr * g / (|g| + eps)
     assert np.allclose(w, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_standardisation_divides_by_the_sd_and_rounds_to_bf16():
+    # values whose standardisation is exact: (3 - 1) / 0.5 = 4, (1 - 0) / 4 =
+    # 0.25, (-2 - 2) / 8 = -0.5; then ones whose BF16 rounding is fixed by the
+    # format: (1 + 2^-8 - 0) / 1 ties to 1.0, (1 + 3 * 2^-8) / 1 to 1 + 2^-6
+    norm = np.array([1.0, 0.0, 2.0, 0.0, 0.0, 0, 0, 0, 0, 0] + [0.5, 4.0, 8.0, 1.0, 1.0, 1, 1, 1, 1, 1],
+                    np.float32)
+    feat = np.array([[3.0, 1.0, -2.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 0, 0, 0, 0, 0]], np.float32)
+    out = oracle.standardize(feat, norm)
+    assert out.shape == (1, 16)
+    assert list(out[0, :5]) == [0x4080, 0x3E80, 0xBF00, 0x3F80, 0x3F82]
+    assert np.all(out[0, 10:] == 0)
