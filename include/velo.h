@@ -269,6 +269,26 @@ int velo_mlp_train_step(velo_ctx* ctx, int64_t n, const uint16_t* d_feat, const 
                         float* d_loss, void* stream);
 int velo_mlp_set_adam(velo_ctx* ctx, float beta1, float beta2, float eps);
 
+/* The gradient of velo_mlp_grad for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc): no context and no allocation of any kind.
+ * The weights come as d_master[1441] FP32 (device, the velo_mlp_set_weights
+ * order); d_feat, d_label, d_grad and d_loss are as for velo_mlp_grad, and
+ * the result is bit-identical to velo_mlp_grad with the same weights.
+ * Scratch: the per-workgroup partial sums go to a device array inside the
+ * library, 1024 x 1472 FP32 (5.75 MiB), one copy per GPU held until the
+ * process ends; the gradient spreads any n over at most 1024 workgroups, so
+ * every n >= 1 fits (a computed workgroup count above 1024 would be rejected
+ * with VELO_ERR_ARG).  Each partial is written before it is read, so nothing
+ * needs clearing between calls.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (two streams, two threads) race and give
+ * wrong gradients; serialise them.  The first call on a device resolves the
+ * array's address on it (no stream work).
+ * Errors: VELO_ERR_ARG for n <= 0 or null arrays, VELO_ERR_DEVICE for a
+ * failed launch (message in velo_last_error). */
+int velo_mlp_grad_noalloc(int64_t n, const float* d_master, const uint16_t* d_feat, const uint8_t* d_label,
+                          float* d_grad, float* d_loss, void* stream);
+
 /* Optimiser state for checkpoints: master[1441], m[1441], v[1441], step. */
 int velo_mlp_get_state(velo_ctx* ctx, float* h_master, float* h_m, float* h_v, int64_t* h_step);
 int velo_mlp_set_state(velo_ctx* ctx, const float* h_master, const float* h_m, const float* h_v, int64_t step);

@@ -453,19 +453,29 @@ hipError_t launch_mlp_forward(const MlpState& m, int64_t n, const uint16_t* feat
 
 // Grid size of the gradient depends on n only, so the reduction order (and the
 // result) is reproducible bit for bit.
-hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const uint8_t* label, float* grad,
-                           float* loss, hipStream_t s) {
+int64_t mlp_grad_blocks(int64_t n) {
     const int64_t tiles = (n + 15) / 16;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(kMaxGradBlocks, (tiles + kGradWaves - 1) / kGradWaves));
+    return std::max<int64_t>(1, std::min<int64_t>(kMaxGradBlocks, (tiles + kGradWaves - 1) / kGradWaves));
+}
+
+hipError_t launch_mlp_grad_part(const float* master, float* part, int64_t n, const uint16_t* feat,
+                                const uint8_t* label, float* grad, float* loss, hipStream_t s) {
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t blocks = mlp_grad_blocks(n);
     const int64_t nwaves = blocks * kGradWaves;
     const int64_t per_wave = (tiles + nwaves - 1) / nwaves;
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)blocks), dim3(kGradThreads), 0, s, m.d_master, n, feat, label,
-                       m.d_part, per_wave);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)blocks), dim3(kGradThreads), 0, s, master, n, feat, label, part,
+                       per_wave);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((kNParam + 1 + kWave - 1) / kWave), dim3(kRedWaves * kWave), 0, s, m.d_part,
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kNParam + 1 + kWave - 1) / kWave), dim3(kRedWaves * kWave), 0, s, part,
                        (int)blocks, grad, loss, 1.0f / (float)n);
     return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const uint8_t* label, float* grad,
+                           float* loss, hipStream_t s) {
+    return launch_mlp_grad_part(m.d_master, m.d_part, n, feat, label, grad, loss, s);
 }
 
 hipError_t launch_adam(MlpState& m, float lr, hipStream_t s) {

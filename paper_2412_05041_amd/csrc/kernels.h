@@ -144,4 +144,7 @@ hipError_t launch_extrapolate(const ExtrapArgs& a, hipStream_t s);
 hipError_t launch_kalman(const KalmanArgs& a, hipStream_t s);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s);
 
+// Records `msg` as this thread's velo_last_error() and returns `code`.
+int set_last_error(int code, const char* msg);
+
 }  // namespace velo

@@ -37,6 +37,12 @@ hipError_t launch_standardize(const float* norm, int64_t n, const float* raw, ui
 hipError_t launch_mlp_forward(const MlpState& m, int64_t n, const uint16_t* feat, float* logit, hipStream_t s);
 hipError_t launch_mlp_grad(MlpState& m, int64_t n, const uint16_t* feat, const uint8_t* label, float* grad,
                            float* loss, hipStream_t s);
+// Same gradient with the master weights and the per-block partials
+// ([mlp_grad_blocks(n)][kGradStride] FP32, fully written before being read)
+// given explicitly; the workgroup count depends on n only.
+int64_t mlp_grad_blocks(int64_t n);
+hipError_t launch_mlp_grad_part(const float* master, float* part, int64_t n, const uint16_t* feat,
+                                const uint8_t* label, float* grad, float* loss, hipStream_t s);
 hipError_t launch_adam(MlpState& m, float lr, hipStream_t s);
 
 int find_blocks_per_cu(int threads, int tile, bool seed);

@@ -289,6 +289,11 @@ int check_reserved(velo_ctx* c, int32_t E, int64_t clusters) {
 
 }  // namespace
 
+int velo::set_last_error(int code, const char* msg) {
+    g_last_error = msg;
+    return code;
+}
+
 extern "C" {
 
 const char* velo_last_error(void) { return g_last_error.c_str(); }

@@ -64,6 +64,7 @@ _SIGS = {
     "velo_mlp_forward": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_standardize": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_mlp_grad": [C.c_void_p, C.c_int64] + [C.c_void_p] * 5,
+    "velo_mlp_grad_noalloc": [C.c_int64] + [C.c_void_p] * 6,
     "velo_mlp_train_step": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
                             C.c_void_p],
     "velo_mlp_set_adam": [C.c_void_p, C.c_float, C.c_float, C.c_float],
