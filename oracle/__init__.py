@@ -17,20 +17,31 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "velo_oracle.cpp")
-LIB = os.path.join(HERE, "libvelo_oracle.so")
+# VELO_ORACLE_SANITIZE=1 loads a build with AddressSanitizer and UBSan (clang,
+# shared sanitizer runtime, which the process must preload)
+SANITIZE = os.environ.get("VELO_ORACLE_SANITIZE") == "1"
+LIB = os.path.join(HERE, "libvelo_oracle_san.so" if SANITIZE else "libvelo_oracle.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-shared-libsan", "-fno-omit-frame-pointer", "-g"]
 
 N_PLANES = 26
 N_PARAM = 1441
 FLAG_PLAIN, FLAG_LEARNED, FLAG_FALLBACK, FLAG_ACCEPT = 1, 2, 4, 8
 
 
-def build(force: bool = False) -> str:
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-std=c++17", SRC, "-o", tmp])
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = False, sanitize: bool = SANITIZE) -> str:
+    """Compiles the oracle; sanitize=True: the clang AddressSanitizer + UBSan build."""
+    lib = os.path.join(HERE, "libvelo_oracle_san.so" if sanitize else "libvelo_oracle.so")
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        if sanitize:
+            cmd = [os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang++"), "-O1",
+                   *SAN_FLAGS]
+        else:
+            cmd = ["g++", "-O2"]
+        subprocess.check_call([*cmd, "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c++17",
+                               SRC, "-o", tmp])
+        os.replace(tmp, lib)
+    return lib
 
 
 class Cuts(C.Structure):

@@ -24,19 +24,43 @@ FLAGS = [
 ]
 
 
+# Host code instrumented with AddressSanitizer and UBSan (each flag behind
+# -Xarch_host: device code is built as usual); the process that loads the
+# library must preload clang's shared sanitizer runtime.
+SAN_LIB = os.path.join(HERE, "libvelo_san.so")
+SAN_HOST = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined -Xarch_host -shared-libsan " \
+           "-Xarch_host -fno-omit-frame-pointer -Xarch_host -g".split()
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *FLAGS, *sources(), "-o", tmp]
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    lib = SAN_LIB if sanitize else LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    flags = list(FLAGS)
+    if sanitize:
+        flags[flags.index("-O3")] = "-O1"
+        flags += SAN_HOST
+    cmd = ["hipcc", *flags, *sources(), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def sanitizer_runtime() -> str:
+    """Path of clang's shared AddressSanitizer runtime (to preload)."""
+    import glob as g
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    hits = sorted(g.glob(os.path.join(rocm, "llvm", "lib", "clang", "*", "lib", "linux",
+                                      "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("clang's shared AddressSanitizer runtime was not found under " + rocm)
+    return hits[-1]
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

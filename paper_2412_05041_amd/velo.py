@@ -13,7 +13,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvelo.so")
+# VELO_SANITIZE=1 loads the build whose host code carries AddressSanitizer and
+# UBSan (build.py --sanitize; the process must preload the sanitizer runtime)
+LIB_PATH = os.path.join(HERE, "libvelo_san.so" if os.environ.get("VELO_SANITIZE") == "1" else "libvelo.so")
 
 N_PLANES = 26
 N_LAUNCH = 12  # finder launch configurations timed by the autotuner

@@ -8,7 +8,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "velo.h")
-LIB = os.path.join(ROOT, "paper_2412_05041_amd", "libvelo.so")
+LIB = os.path.join(ROOT, "paper_2412_05041_amd",
+                   "libvelo_san.so" if os.environ.get("VELO_SANITIZE") == "1" else "libvelo.so")
 
 
 def declared():
@@ -21,7 +22,7 @@ def declared():
 def lib():
     if not os.path.exists(LIB):
         from paper_2412_05041_amd import build
-        build.build()
+        build.build(sanitize=os.environ.get("VELO_SANITIZE") == "1")
     return C.CDLL(LIB)
 
 
