@@ -33,22 +33,42 @@ METRIC = "VELO events/s at nominal occupancy (1 GPU), eff/ghost rate; % HBM roof
 
 
 def _oracle_chunk(args):
-    """CPU baseline worker: the oracle (cluster + find + FP64 fit) on an event slice."""
+    """CPU baseline worker: the oracle (cluster + find + FP64 fit) on an event slice.
+    Returns (events, the finder's brute-force test counts: pairs, triplets, seed candidates)."""
     import numpy as np  # noqa: F401
     import oracle
     pix_off, pix_id, plane_z, cuts, seed = args
     c = oracle.cluster(pix_off, pix_id)
     t = oracle.find_tracks(c["clu_off"], c["clu_x"], c["clu_y"], plane_z, cuts, seed=seed)
     oracle.fit(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], plane_z, cuts["sigma"])
-    return int(pix_off.size - 1) // 26
+    return int(pix_off.size - 1) // 26, [int(x) for x in t["stats"][:3]]
+
+
+# Worker processes of the CPU baseline: the host CPUs this process may run on,
+# at most 16 -- the host share that goes with one GPU on a shared GPU box.
+MAX_CPU_WORKERS = 16
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(batch, cuts, passes, min_wall, seed=None):
+    """The oracle on the host: event-parallel over the worker processes, and on
+    one process over a slice of the batch.  Also returns the method's test
+    counts per event (brute-force pairs and triplets, from the oracle)."""
     import multiprocessing as mp
 
     import oracle
     oracle.build()
-    cores = max(1, min(16, os.cpu_count() or 1))
+    avail = len(os.sched_getaffinity(0))
+    cores = max(1, min(MAX_CPU_WORKERS, avail))
     chunks = []
     step = max(1, batch.n_events // (cores * 4))
     for e0 in range(0, batch.n_events, step):
@@ -59,14 +79,35 @@ def cpu_baseline(batch, cuts, passes, min_wall, seed=None):
         pool.map(_oracle_chunk, chunks[:cores])  # warm the workers
         t0 = time.perf_counter()
         n = done = 0
+        tests = None
         while done < passes or time.perf_counter() - t0 < min_wall:
-            n += sum(pool.map(_oracle_chunk, chunks))
+            res = pool.map(_oracle_chunk, chunks)
+            n += sum(r[0] for r in res)
+            if tests is None:
+                tests = [sum(r[1][i] for r in res) for i in range(3)]
             done += 1
         dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="events/s", cores=cores, kind="oracle",
-                sample=f"all {batch.n_events} events of the benchmark batch x {done} passes "
+    # one process, the first chunk (warm: the pool already ran the oracle once here)
+    one = chunks[0]
+    _oracle_chunk(one)
+    t1 = time.perf_counter()
+    n1 = reps1 = 0
+    while reps1 < 1 or time.perf_counter() - t1 < min(min_wall, 1.0):
+        n1 += _oracle_chunk(one)[0]
+        reps1 += 1
+    dt1 = time.perf_counter() - t1
+    E = batch.n_events
+    base = dict(value=n / dt, unit="events/s", cores=cores, kind="oracle",
+                sample=f"all {E} events of the benchmark batch x {done} passes "
                        f"(cluster + find + FP64 fit), event-parallel over {cores} worker processes; "
-                       f"{dt:.2f} s wall, ~{dt * cores:.0f} s of CPU work")
+                       f"{dt:.2f} s wall, ~{dt * cores:.0f} s of CPU work",
+                host_cpus_available=avail, host_cpu_count=os.cpu_count(), cpu_model=cpu_model(),
+                workers_rule=f"min({MAX_CPU_WORKERS}, CPUs this process may run on)",
+                one_thread=dict(value=n1 / dt1, unit="events/s",
+                                sample=f"events 0..{int(one[0].size - 1) // 26 - 1} x {reps1} passes on one "
+                                       f"process, {dt1:.2f} s"))
+    per_event = dict(pair_tests=tests[0] / E, triplet_tests=tests[1] / E, seed_candidates=tests[2] / E)
+    return base, per_event
 
 
 def log(msg):
@@ -89,6 +130,23 @@ def measured_traffic(kernel, launch, workload):
     if rec["kernel"] != kernel or list(rec["launch"]) != list(launch) or h.hexdigest() != rec["sources_sha256"]:
         return None
     return float(rec["traffic_bytes_per_launch"])
+
+
+def device_copy_gbs(torch, device, mib=1024, reps=10):
+    """Attainable HBM bandwidth: a device-to-device copy of `mib` MiB (read +
+    write bytes / time), HIP events on the current stream."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def describe(w, clusters_per_event):
@@ -152,10 +210,11 @@ def main():
         d = np.load(os.path.join(cfg, "seed_default.npz"), allow_pickle=False)
         seed_net = (d["weights"].astype(np.float32), d["norm"].astype(np.float32), float(d["threshold"]))
 
-    cpu = None
+    cpu = tests_per_event = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, cuts, args.cpu_passes, args.cpu_seconds, seed=seed_net)
-        log(f"cpu baseline: {cpu['value']:.0f} events/s on {cpu['cores']} cores")
+        cpu, tests_per_event = cpu_baseline(batch, cuts, args.cpu_passes, args.cpu_seconds, seed=seed_net)
+        log(f"cpu baseline: {cpu['value']:.0f} events/s on {cpu['cores']} cores "
+            f"({cpu['one_thread']['value']:.0f} on one)")
 
     import torch
 
@@ -176,16 +235,6 @@ def main():
 
     v = new_context()
     off, ids = velo.to_device(batch)
-    tune_ms = None
-    if args.launch:
-        th, tl = (int(x) for x in args.launch.split(","))
-        v.set_launch(th, tl)
-    elif not args.no_autotune:
-        c = v.cluster(off, ids, with_npix=False)
-        tune_ms, _ = v.autotune(c["clu_off"], c["clu_x"], c["clu_y"], reps=2)
-        del c
-    else:
-        tune_ms = None
 
     bank = None
     if args.raw:
@@ -236,11 +285,21 @@ def main():
                 self.extrapolate()
 
     lanes = [Lane(v)]
-    th0, tl0 = v.get_launch()
     for _ in range(args.streams - 1):
-        c = new_context()
-        c.set_launch(th0, tl0)
-        lanes.append(Lane(c))
+        lanes.append(Lane(new_context()))
+    tune_ms = None
+    if args.launch:
+        th, tl = (int(x) for x in args.launch.split(","))
+        for L in lanes:
+            L.v.set_launch(th, tl)
+    elif not args.no_autotune:
+        # the library's autotuner, timing each launch with all batches in flight
+        c = v.cluster(off, ids, with_npix=False)
+        torch.cuda.synchronize()
+        tune_ms, launch = velo.autotune([L.v for L in lanes], c["clu_off"], c["clu_x"], c["clu_y"], reps=8,
+                                        streams=[L.stream for L in lanes])
+        del c
+        log(f"autotune with {len(lanes)} batches in flight: {launch}")
     torch.cuda.synchronize()
     log(f"launch {v.get_launch()}, {args.streams} batch(es) in flight, warm-up")
 
@@ -256,30 +315,6 @@ def main():
                 L.step()
         for L in lanes:
             cur.wait_stream(L.stream)
-
-    sweep = None
-    if len(lanes) > 1 and not args.launch and not args.no_autotune:
-        # The library's autotuner times one batch at a time.  With several in
-        # flight the best launch can differ (a small first tile keeps more events
-        # in flight, and its spill-over to the larger tile overlaps the other
-        # batches), so every configuration is also timed the way the timed
-        # region runs, and the fastest is kept.
-        sweep = {}
-        for sth in (64, 128, 256, 512):
-            for stl in (0, 1, 2):
-                for L in lanes:
-                    L.v.set_launch(sth, stl)
-                run(len(lanes))
-                torch.cuda.synchronize()
-                ts = time.perf_counter()
-                run(8 * len(lanes))
-                torch.cuda.synchronize()
-                sweep[f"{sth},{stl}"] = (time.perf_counter() - ts) * 1e3 / (8 * len(lanes))
-        best = min(sweep, key=sweep.get)
-        bth, btl = (int(x) for x in best.split(","))
-        for L in lanes:
-            L.v.set_launch(bth, btl)
-        log(f"launch with {len(lanes)} batches in flight: {best} ({sweep[best]:.3f} ms per batch)")
 
     run(max(args.warmup, len(lanes)))
     torch.cuda.synchronize()
@@ -389,6 +424,20 @@ def main():
         "output_fit": 12 * H + 40 * T,                    # gather hits, write CSR + 8-float state
     }
     achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
+    copy_gbs = device_copy_gbs(torch, v.device)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
+    alu = None
+    if tests_per_event is not None:
+        alu = {
+            "definition": "the method's brute-force tests (oracle count): every unused (h0, h2) pair of a "
+                          "seeding step, every unused middle hit of a pair that passes the pair cuts; the "
+                          "GPU's windowed search evaluates the cut only on a subset of them",
+            "pair_tests_per_event": tests_per_event["pair_tests"],
+            "triplet_tests_per_event": tests_per_event["triplet_tests"],
+            "seed_candidates_per_event": tests_per_event["seed_candidates"],
+            "pair_tests_per_s": tests_per_event["pair_tests"] * value,
+            "triplet_tests_per_s": tests_per_event["triplet_tests"] * value,
+        }
     path_bytes = 8 * n_pix + 8 * n_clu + 4 * H + 36 * T  # fused minimum of the whole path
     th, tl = v.get_launch()
     out = {
@@ -417,9 +466,9 @@ def main():
             "extrapolate": bool(args.extrapolate),
             "raw_banks": bool(args.raw),
             "launch": {"threads_per_event": th, "tile": tl},
-            "autotune_ms": tune_ms,
+            "autotune_ms_per_batch": tune_ms,
+            "autotune": "velo_autotune, every launch timed with all batches in flight",
             "batches_in_flight": args.streams,
-            "launch_sweep_ms_per_batch": sweep,
         },
         "efficiency": m["efficiency"],
         "ghost_rate": m["ghost_rate"],
@@ -435,7 +484,10 @@ def main():
             "alg_bytes": alg[dom],
             "launch_ms": stages[dom],
             "launch_timing": "HIP events around the kernel on its stream, one batch in flight",
+            "attainable_copy_GBs": copy_gbs,
+            "frac_of_attainable": achieved / copy_gbs,
         },
+        "alu": alu,
         "path_hbm_frac": path_bytes / E * value / (HBM_PEAK_GBS * 1e9),
         "stages_ms": stages,
         "events_second_tile_or_large": int(ev_rest.sum()),

@@ -120,8 +120,10 @@ int velo_create(const velo_geometry* geometry, const velo_cuts* cuts, int device
 void velo_destroy(velo_ctx* ctx);
 int velo_set_cuts(velo_ctx* ctx, const velo_cuts* cuts);
 
-/* 1 = check pixel inputs (ids < 1454^2, strictly ascending per segment) and
- * flag VELO_EV_BAD_INPUT instead of clustering malformed segments. */
+/* 1 = check pixel inputs (ids < 1454^2, outside the central hole -- pixel
+ * (c, r) exists iff (2c - 1453)^2 + (2r - 1453)^2 >= 33058 --, strictly
+ * ascending per segment) and flag VELO_EV_BAD_INPUT instead of clustering
+ * malformed segments. */
 int velo_set_validate(velo_ctx* ctx, int32_t on);
 
 /* The only call that allocates the internal workspace (velo_create allocates
@@ -224,17 +226,33 @@ int velo_last_timing(velo_ctx* ctx, float* h_ms, int32_t n);
 int velo_set_launch(velo_ctx* ctx, int32_t threads, int32_t tile);
 int velo_get_launch(velo_ctx* ctx, int32_t* threads, int32_t* tile);
 
-/* Times every launch configuration on the given clusters (device inputs, as
- * for velo_find_tracks) and keeps the fastest.  Synchronises the stream.  It
- * times one batch at a time; a caller that keeps several batches in flight
- * (one context and stream each) may find another launch faster -- a small
- * first tile, whose second pass overlaps the other batches -- and should time
- * the candidates that way (bench.py does).
- * h_ms (nullable) receives VELO_N_LAUNCH timings, threads-major (64, 128,
- * 256, 512) then tile. */
+/* Autotuner of the finder's launch (pattern: batches of uneven events in one
+ * persistent launch, threads per event and LDS tile chosen by timing).  Times
+ * each of the VELO_N_LAUNCH configurations with n_ctx batches in flight, the
+ * way a caller that keeps several batches going (one context and stream each)
+ * runs them: context i works on streams[i] -- event lists, the finder passes,
+ * the plain acceptance, over the clusters given (device inputs, as for
+ * velo_find_tracks, read-only and shared) -- all streams concurrently, `reps`
+ * batches per context after one warm-up batch; the time per batch is the
+ * span from the first to the last batch divided by reps * n_ctx.  The fastest
+ * configuration is set on every context.  Synchronises the streams.
+ *   ctxs[n_ctx]: distinct contexts on one device, each reserved for n_events
+ *     (1 <= n_ctx <= 16); streams[n_ctx]: hipStream_t of each (NULL = default).
+ *   cache_path (nullable): a text file, one line per pick ("<key>\t<threads>
+ *     <tile> <ms per batch>").  The key names the device (architecture, CU
+ *     count), n_events, the clusters per event in quarter-octave buckets,
+ *     n_ctx, and a hash of the cuts, plane positions and seed-filter state.  A
+ *     line with the same key is applied without timing (h_ms then all -1);
+ *     otherwise the pick is appended.
+ *   h_ms (nullable): VELO_N_LAUNCH timings, threads-major (64, 128, 256, 512)
+ *     then tile.
+ * Errors: VELO_ERR_ARG for bad arguments or a cache file that cannot be
+ * appended to (the pick is set all the same); on any other error every
+ * context keeps the launch it had. */
 #define VELO_N_LAUNCH 12
-int velo_autotune(velo_ctx* ctx, int32_t n_events, const int32_t* d_clu_off, const float* d_clu_x,
-                  const float* d_clu_y, int32_t reps, float* h_ms, void* stream);
+int velo_autotune(velo_ctx* const* ctxs, int32_t n_ctx, int32_t n_events, const int32_t* d_clu_off,
+                  const float* d_clu_x, const float* d_clu_y, int32_t reps, const char* cache_path, float* h_ms,
+                  void* const* streams);
 
 /* Learned filter.  Parameters: 1441 FP32 master weights in the order
  * W1[32][10], b1[32], W2[32][32], b2[32], w3[32], b3; normalisation: 10 means

@@ -8,6 +8,9 @@ namespace velo {
 
 constexpr int kPlanes = 26;
 constexpr int kSide = 1454;
+// Central hole of a plane: pixel (column c, row r) exists iff
+// (2c - 1453)^2 + (2r - 1453)^2 >= kHoleD2 (a 5 mm radius in half-pixel units).
+constexpr int kHoleD2 = 33058;
 constexpr int kStatusHdr = 8;
 // Square grid over the sensor plane for disc searches on crowded planes:
 // 0.5 mm cells over [-40, 40] mm in x and y.

@@ -50,6 +50,13 @@ __device__ __forceinline__ void unite(P* par, int a, int b) {
     }
 }
 
+// A pixel id the sensor has: below 1454^2 and outside the central hole.
+__device__ __forceinline__ bool valid_pixel(uint32_t id) {
+    if (id >= (uint32_t)(kSide * kSide)) return false;
+    const int dc = 2 * (int)(id % kSide) - (kSide - 1), dr = 2 * (int)(id / kSide) - (kSide - 1);
+    return dc * dc + dr * dr >= kHoleD2;
+}
+
 template <typename Id>
 __device__ __forceinline__ int lower_bound_u32(const Id* a, int n, uint32_t v) {
     int lo = 0, hi = n;
@@ -141,7 +148,7 @@ __device__ void cluster_global(const ClusterArgs& a, int seg, int p0, int n, con
     if (a.validate && !refuse) {
         for (int i = lane; i < n; i += kWave) {
             const uint32_t id = ids[i];
-            if (id >= (uint32_t)(kSide * kSide) || (i > 0 && ids[i - 1] >= id)) bad = 1;
+            if (!valid_pixel(id) || (i > 0 && ids[i - 1] >= id)) bad = 1;
         }
     }
     bad = __syncthreads_or(bad);
@@ -220,7 +227,7 @@ __device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsi
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = lane + r * kWave;
-            if (i < n && (id[r] >= (uint32_t)(kSide * kSide) || (i > 0 && s_id[i - 1] >= id[r]))) bad = 1;
+            if (i < n && (!valid_pixel(id[r]) || (i > 0 && s_id[i - 1] >= id[r]))) bad = 1;
         }
     }
     if (__syncthreads_or(bad)) {

@@ -278,6 +278,125 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     return VELO_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+
+constexpr int kMaxInFlight = 16;
+
+// Launch state of the contexts being tuned and the timing events: on any exit
+// before commit() the contexts get their launches back and the events are freed.
+struct TuneScope {
+    velo_ctx* const* ctxs;
+    int n;
+    int th[kMaxInFlight], tl[kMaxInFlight];
+    hipEvent_t e0 = nullptr, e1 = nullptr, join[kMaxInFlight] = {};
+    bool ok = true, done = false;
+    TuneScope(velo_ctx* const* c, int n_) : ctxs(c), n(n_) {
+        for (int i = 0; i < n; ++i) { th[i] = c[i]->threads; tl[i] = c[i]->tile; }
+        ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        for (int i = 0; ok && i < n; ++i) ok = hipEventCreateWithFlags(&join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    void commit(int threads, int tile) {
+        for (int i = 0; i < n; ++i) {
+            ctxs[i]->threads = threads;
+            ctxs[i]->tile = tile;
+            ctxs[i]->version++;
+        }
+        done = true;
+    }
+    ~TuneScope() {
+        if (!done)
+            for (int i = 0; i < n; ++i) { ctxs[i]->threads = th[i]; ctxs[i]->tile = tl[i]; ctxs[i]->version++; }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (int i = 0; i < n; ++i)
+            if (join[i]) (void)hipEventDestroy(join[i]);
+    }
+};
+
+// Stream 0 waits for the work queued so far on the other streams.
+hipError_t join_streams(TuneScope& sc, void* const* streams, int n) {
+    for (int i = 1; i < n; ++i) {
+        hipError_t e = hipEventRecord(sc.join[i], (hipStream_t)streams[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)streams[0], sc.join[i], 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One batch of the tuned work on a context: event lists, the finder passes
+// and the acceptance (plain cut; it does not depend on the launch).
+int enqueue_tune_batch(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* clu_x, const float* clu_y,
+                       hipStream_t s) {
+    HIP_OK(launch_reset(c->w, E, nullptr, s));
+    HIP_OK(enqueue_order(c, E, clu_off, s));
+    FindArgs fa{};
+    fa.n_events = E;
+    fa.clu_off = clu_off;
+    fa.clu_x = clu_x;
+    fa.clu_y = clu_y;
+    fa.status = nullptr;
+    fa.p = c->p;
+    fa.p.mode = 0;
+    fa.w = c->w;
+    fa.clu_limit = c->w.cap_clusters;
+    fa.seed_net = c->seed_on ? c->d_seed : nullptr;
+    if (int rc = enqueue_finder(c, fa, E, s, false)) return rc;
+    HIP_OK(launch_accept(fa, s));
+    return VELO_OK;
+}
+
+// Cache key: device, batch shape (events; clusters per event in quarter-octave
+// buckets), batches in flight, and everything of the context that changes the
+// finder's work (cuts, plane positions, seed filter).
+std::string tune_key(const hipDeviceProp_t& prop, const velo_ctx* c, int n_ctx, int32_t E, int32_t n_clu) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the finder's parameters
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    mix(&c->p, sizeof(Params));
+    const int seed = c->seed_on;
+    mix(&seed, sizeof(seed));
+    const double cpe = (double)n_clu / (double)E;
+    const int bucket = cpe > 0.0 ? (int)std::lround(4.0 * std::log2(cpe)) : -1000;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s/%dcu events=%d clu_bucket=%d in_flight=%d params=%016llx", prop.gcnArchName,
+             prop.multiProcessorCount, E, bucket, n_ctx, (unsigned long long)h);
+    for (char* q = buf; *q; ++q)
+        if (*q == '\t' || *q == '\n') *q = ' ';
+    return buf;
+}
+
+// Cache file: one line per pick, "<key>\t<threads> <tile> <ms>"; the last line
+// of a key wins.
+bool tune_cache_lookup(const char* path, const std::string& key, int* th, int* tl) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool hit = false;
+    while (fgets(line, sizeof(line), f)) {
+        char* tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        int a = 0, b = 0;
+        if (key == line && sscanf(tab + 1, "%d %d", &a, &b) == 2 && (a == 64 || a == 128 || a == 256 || a == 512) &&
+            b >= 0 && b <= 2) {
+            *th = a;
+            *tl = b;
+            hit = true;
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
+bool tune_cache_append(const char* path, const std::string& key, int th, int tl, float ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return false;
+    const bool ok = fprintf(f, "%s\t%d %d %.6f\n", key.c_str(), th, tl, ms) > 0;
+    return (fclose(f) == 0) && ok;
+}
+
 int check_reserved(velo_ctx* c, int32_t E, int64_t clusters) {
     if (E < 0) return fail(VELO_ERR_ARG, "n_events < 0");
     if (E > c->w.cap_events) return fail(VELO_ERR_NOT_RESERVED, "n_events %d > reserved %d", E, c->w.cap_events);
@@ -342,13 +461,13 @@ int velo_create(const velo_geometry* g, const velo_cuts* cu, int device, velo_ct
 
 void velo_destroy(velo_ctx* c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
-    if (c->exec) hipGraphExecDestroy(c->exec);
-    if (c->ws) hipFree(c->ws);
-    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (int i = 0; i <= VELO_N_STAGES; ++i)
-        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     mlp_free(c->mlp);
     if (c->d_seed) (void)hipFree(c->d_seed);
     delete c;
@@ -634,10 +753,10 @@ int velo_pipeline(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t
                                   trk_logit, par, trk_cap, hit_cap, 0, status, clu_cap, cs);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &g);
-        if (rc) { if (g) hipGraphDestroy(g); return rc; }
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
         if (e != hipSuccess) return fail(VELO_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) { c->exec = nullptr; return fail(VELO_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
         c->key = key;
     }
@@ -645,61 +764,86 @@ int velo_pipeline(velo_ctx* c, int32_t E, const int32_t* pix_off, const uint32_t
     return VELO_OK;
 }
 
-int velo_autotune(velo_ctx* c, int32_t E, const int32_t* clu_off, const float* clu_x, const float* clu_y,
-                  int32_t reps, float* h_ms, void* stream) {
-    if (int rc = check_ctx(c)) return rc;
+int velo_autotune(velo_ctx* const* ctxs, int32_t n_ctx, int32_t E, const int32_t* clu_off, const float* clu_x,
+                  const float* clu_y, int32_t reps, const char* cache_path, float* h_ms, void* const* streams) {
+    if (!ctxs || n_ctx <= 0 || n_ctx > kMaxInFlight || !streams)
+        return fail(VELO_ERR_ARG, "need 1..%d contexts and their streams", kMaxInFlight);
     if (E <= 0 || !clu_off || !clu_x || !clu_y || reps <= 0) return fail(VELO_ERR_ARG, "bad arguments");
-    if (int rc = check_reserved(c, E, 0)) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int threads[4] = {64, 128, 256, 512};
-    float best = 1e30f;
-    int bt = c->threads, bl = c->tile;
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    // staging once; the finder leaves it unchanged except for the used flags,
-    // which every event resets when its planes are loaded
-    HIP_OK(launch_reset(c->w, E, nullptr, s));
-    StageArgs sa{E * kPlanes, clu_off, clu_x, clu_y, c->w};
-    HIP_OK(launch_stage(sa, s));
-    int idx = 0;
-    for (int ti = 0; ti < 4; ++ti) {
-        for (int tl = 0; tl < 3; ++tl, ++idx) {
-            c->threads = threads[ti];
-            c->tile = tl;
-            FindArgs fa{};
-            fa.n_events = E;
-            fa.clu_off = clu_off;
-            fa.clu_x = clu_x;
-            fa.clu_y = clu_y;
-            fa.status = nullptr;
-            fa.p = c->p;
-            fa.p.mode = 0;
-            fa.w = c->w;
-            fa.clu_limit = c->w.cap_clusters;
-            fa.seed_net = c->seed_on ? c->d_seed : nullptr;
-            float tot = 0.0f;
-            for (int r = 0; r <= reps; ++r) {
-                HIP_OK(launch_reset(c->w, E, nullptr, s));
-                HIP_OK(enqueue_order(c, E, clu_off, s));
-                HIP_OK(hipEventRecord(e0, s));
-                if (int rc = enqueue_finder(c, fa, E, s, false)) return rc;
-                HIP_OK(hipEventRecord(e1, s));
-                HIP_OK(hipEventSynchronize(e1));
-                float ms = 0.0f;
-                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-                if (r > 0) tot += ms;  // first run warms up
+    for (int i = 0; i < n_ctx; ++i) {
+        if (int rc = check_ctx(ctxs[i])) return rc;
+        if (int rc = check_reserved(ctxs[i], E, 0)) return rc;
+        if (ctxs[i]->device != ctxs[0]->device) return fail(VELO_ERR_ARG, "contexts on different devices");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(VELO_ERR_ARG, "a context appears twice");
+    }
+    velo_ctx* c0 = ctxs[0];
+    HIP_OK(hipSetDevice(c0->device));
+    // the batch's shape for the cache key: its cluster count (synchronous read)
+    int32_t n_clu = 0;
+    HIP_OK(hipMemcpy(&n_clu, clu_off + (int64_t)E * kPlanes, sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::string key;
+    if (cache_path) {
+        hipDeviceProp_t prop;
+        HIP_OK(hipGetDeviceProperties(&prop, c0->device));
+        key = tune_key(prop, c0, n_ctx, E, n_clu);
+        int th = 0, tl = 0;
+        if (tune_cache_lookup(cache_path, key, &th, &tl)) {
+            for (int i = 0; i < n_ctx; ++i) {
+                ctxs[i]->threads = th;
+                ctxs[i]->tile = tl;
+                ctxs[i]->version++;
             }
-            tot /= (float)reps;
-            if (h_ms) h_ms[idx] = tot;
-            if (tot < best) { best = tot; bt = threads[ti]; bl = tl; }
+            if (h_ms)
+                for (int i = 0; i < VELO_N_LAUNCH; ++i) h_ms[i] = -1.0f;
+            return VELO_OK;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    c->threads = bt;
-    c->tile = bl;
-    c->version++;
+    TuneScope scope(ctxs, n_ctx);  // restores every launch and frees the events on any early return
+    if (!scope.ok) return fail(VELO_ERR_DEVICE, "hipEventCreate failed");
+    hipStream_t s0 = (hipStream_t)streams[0];
+    // staging once per context; the finder changes only the used flags, which
+    // every event resets when its planes are loaded
+    for (int i = 0; i < n_ctx; ++i) {
+        hipStream_t s = (hipStream_t)streams[i];
+        HIP_OK(launch_reset(ctxs[i]->w, E, nullptr, s));
+        StageArgs sa{E * kPlanes, clu_off, clu_x, clu_y, ctxs[i]->w};
+        HIP_OK(launch_stage(sa, s));
+    }
+    const int threads[4] = {64, 128, 256, 512};
+    float best = 1e30f;
+    int bt = c0->threads, bl = c0->tile, idx = 0;
+    for (int ti = 0; ti < 4; ++ti) {
+        for (int tl = 0; tl < 3; ++tl, ++idx) {
+            for (int i = 0; i < n_ctx; ++i) {
+                ctxs[i]->threads = threads[ti];
+                ctxs[i]->tile = tl;
+            }
+            // one warm-up batch per context, then reps batches per context, the
+            // contexts' streams running concurrently between two joins on stream 0
+            for (int r = 0; r <= reps; ++r) {
+                if (r == 1) {
+                    HIP_OK(join_streams(scope, streams, n_ctx));
+                    HIP_OK(hipEventRecord(scope.e0, s0));
+                    for (int i = 1; i < n_ctx; ++i) HIP_OK(hipStreamWaitEvent((hipStream_t)streams[i], scope.e0, 0));
+                }
+                for (int i = 0; i < n_ctx; ++i)
+                    if (int rc = enqueue_tune_batch(ctxs[i], E, clu_off, clu_x, clu_y, (hipStream_t)streams[i]))
+                        return rc;
+            }
+            HIP_OK(join_streams(scope, streams, n_ctx));
+            HIP_OK(hipEventRecord(scope.e1, s0));
+            HIP_OK(hipEventSynchronize(scope.e1));
+            float ms = 0.0f;
+            HIP_OK(hipEventElapsedTime(&ms, scope.e0, scope.e1));
+            ms /= (float)(reps * n_ctx);
+            if (h_ms) h_ms[idx] = ms;
+            if (ms < best) { best = ms; bt = threads[ti]; bl = tl; }
+        }
+    }
+    scope.commit(bt, bl);
+    if (cache_path && !tune_cache_append(cache_path, key, bt, bl, best))
+        return fail(VELO_ERR_ARG, "cannot append to the autotune cache %s (launch %d x tile %d was set)", cache_path,
+                    bt, bl);
     return VELO_OK;
 }
 

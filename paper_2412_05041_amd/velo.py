@@ -54,8 +54,8 @@ _SIGS = {
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
     "velo_get_launch": [C.c_void_p, C.c_void_p, C.c_void_p],
-    "velo_autotune": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
-                      C.c_void_p],
+    "velo_autotune": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                      C.c_char_p, C.c_void_p, C.c_void_p],
     "velo_mlp_set_weights": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_seed_filter_set": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float],
     "velo_extrapolate": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -298,32 +298,9 @@ class Velo:
                                    b["hit_cap"], _ptr(b["status"]), _stream()))
         return bufs
 
-    def autotune(self, clu_off, clu_x, clu_y, reps=3, cache=None, key=None):
-        """Times the N_LAUNCH finder launch configurations on these clusters and keeps
-        the fastest.  With cache (a JSON file) and key (a workload label), a
-        stored choice for (device arch, CU count, key) is reused instead."""
-        ident = None
-        if cache is not None and key is not None:
-            import json
-            p = torch.cuda.get_device_properties(self.device)
-            ident = f"{getattr(p, 'gcnArchName', p.name)}|{p.multi_processor_count}|{N_LAUNCH}|{key}"
-            table = json.load(open(cache)) if os.path.exists(cache) else {}
-            if ident in table:
-                th, tl = table[ident]["launch"]
-                self.set_launch(th, tl)
-                return table[ident]["ms"], (th, tl)
-        E = (clu_off.numel() - 1) // N_PLANES
-        ms = (C.c_float * N_LAUNCH)()
-        _check(lib().velo_autotune(self.h, E, _ptr(clu_off), _ptr(clu_x), _ptr(clu_y), reps, ms, _stream()))
-        res = (list(ms), self.get_launch())
-        if ident is not None:
-            import json
-            table = json.load(open(cache)) if os.path.exists(cache) else {}
-            table[ident] = {"launch": list(res[1]), "ms": res[0]}
-            tmp = cache + ".tmp"
-            json.dump(table, open(tmp, "w"), indent=1)
-            os.replace(tmp, cache)
-        return res
+    def autotune(self, clu_off, clu_x, clu_y, reps=3, cache=None):
+        """velo_autotune on this context alone (current stream); see autotune()."""
+        return autotune([self], clu_off, clu_x, clu_y, reps=reps, cache=cache)
 
     STAGES = ("reset", "cluster", "order", "find_lds", "find_large", "accept", "scan", "output_fit")
 
@@ -432,6 +409,23 @@ class Velo:
     def mlp_set_state(self, master, m, v, step):
         arrs = [np.ascontiguousarray(x, np.float32) for x in (master, m, v)]
         _check(lib().velo_mlp_set_state(self.h, *[x.ctypes.data_as(C.c_void_p) for x in arrs], int(step)))
+
+
+def autotune(ctxs, clu_off, clu_x, clu_y, reps=3, cache=None, streams=None):
+    """velo_autotune: times the N_LAUNCH finder launches with len(ctxs) batches
+    in flight (context i on streams[i], default: the current stream for all),
+    sets the fastest on every context.  cache: path of the library's text cache.
+    Returns (ms per batch of each configuration, or -1s on a cache hit; launch)."""
+    n = len(ctxs)
+    E = (clu_off.numel() - 1) // N_PLANES
+    hs = (C.c_void_p * n)(*[c.h.value for c in ctxs])
+    if streams is None:
+        streams = [torch.cuda.current_stream()] * n
+    ss = (C.c_void_p * n)(*[s.cuda_stream for s in streams])
+    ms = (C.c_float * N_LAUNCH)()
+    _check(lib().velo_autotune(hs, n, E, _ptr(clu_off), _ptr(clu_x), _ptr(clu_y), reps,
+                               None if cache is None else os.fsencode(cache), ms, ss))
+    return list(ms), ctxs[0].get_launch()
 
 
 def to_device(batch, device="cuda"):

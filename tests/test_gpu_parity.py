@@ -220,6 +220,22 @@ def test_validate_mode_flags_malformed_segments(velo_mod):
     s = b.pix_off[26 + 15]  # event 1, plane 15: swap two ids
     assert b.pix_off[26 + 16] - s >= 2
     ids[s], ids[s + 1] = ids[s + 1], ids[s]
+    # event 2: one pixel moved into the central hole, between its neighbours'
+    # ids so that the segment stays strictly ascending
+    hole = np.array([r * 1454 + c for r in range(630, 824) for c in range(630, 824)
+                     if (2 * c - 1453) ** 2 + (2 * r - 1453) ** 2 < 33058])
+    moved = False
+    for p in range(26):
+        lo, hi = b.pix_off[2 * 26 + p], b.pix_off[2 * 26 + p + 1]
+        for i in range(lo + 1, hi - 1):
+            inside = hole[(hole > ids[i - 1]) & (hole < ids[i + 1])]
+            if inside.size:
+                ids[i] = inside[0]
+                moved = True
+                break
+        if moved:
+            break
+    assert moved
     b.pix_id = ids
     v = velo_mod.Velo(b.plane_z, cuts("default"))
     v.set_validate(True)
@@ -228,4 +244,4 @@ def test_validate_mode_flags_malformed_segments(velo_mod):
     gc = v.cluster(off, idt)
     torch.cuda.synchronize()
     st = v.read_status(gc["status"])
-    assert st[0] == 2 and st[8 + 1] & 2 and not (st[8] & 2) and not (st[8 + 2] & 2)
+    assert st[0] == 2 and st[8 + 1] & 2 and st[8 + 2] & 2 and not (st[8] & 2)
