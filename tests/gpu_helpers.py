@@ -8,6 +8,7 @@ import oracle
 from paper_2412_05041_amd import gen
 
 CFG = os.path.join(os.path.dirname(__file__), "..", "paper_2412_05041_amd", "configs")
+HOLE_RADIUS_MM = 5.0
 
 
 def cuts(name):
@@ -71,24 +72,30 @@ def track_scales(t, c):
 
 
 def assert_fit_close(par32, t, c, plane_z, sigma):
-    """FP32 device fit vs the FP64 oracle fit.  Positions within 1e-5 of the
-    track's largest hit radius, slopes within 1e-5 of max(|t|, largest hit
-    offset / z span), z_ref within 1e-5 of the largest |z| of its planes, chi2 within 1e-3 of
-    max(chi2, 1) (a statistic of ~10 mm differences), ndof exact.  The device
-    fit must also equal the oracle's FP32 fit (same operations, same order) bit
-    for bit."""
+    """FP32 device fit vs the FP64 oracle fit, 1e-5 relative to the state:
+    x_ref, y_ref (the FP64 line at the device's z_ref) within 1e-5 of
+    max(|(x, y)|, 5 mm) -- 5 mm, the hole radius, is the smallest distance of a
+    hit from the axis and so the smallest magnitude the FP32 sums of hit
+    coordinates work at (a noise-made track can pass the axis at its centroid);
+    tx, ty within 1e-5 of |(tx, ty)|; z_ref within 1e-5 of the largest |z| of its
+    planes (a mean of plane positions that may straddle z = 0); ndof exact.
+    chi2 within 1e-3 of max(chi2, 1): it sums squared residuals of ~0.01 mm
+    taken between coordinates of ~10 mm, so FP32 rounding of the coordinates
+    alone moves it by ~1e-4 relative -- 1e-5 is out of reach of any FP32 fit.
+    The device fit must also equal the oracle's FP32 fit (same operations,
+    same order) bit for bit."""
     p64 = oracle.fit(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], plane_z, sigma)
     p32o = oracle.fit(t["trk_hit_off"], t["trk_hit"], t["trk_planes"], c["clu_x"], c["clu_y"], plane_z, sigma,
                       fp64=False).astype(np.float32)
     assert np.array_equal(par32[:, :7].view(np.int32), p32o[:, :7].view(np.int32)), "FP32 fit bits"
     p = par32.astype(np.float64)
-    rmax, dev, first, last = track_scales(t, c)
-    zspan = plane_z[last].astype(np.float64) - plane_z[first].astype(np.float64)
+    _, _, first, last = track_scales(t, c)
     x64 = p64[:, 0] + p64[:, 3] * (p[:, 2] - p64[:, 2])
     y64 = p64[:, 1] + p64[:, 4] * (p[:, 2] - p64[:, 2])
-    tscale = np.maximum(np.hypot(p64[:, 3], p64[:, 4]), dev / zspan)
-    assert np.all(np.abs(p[:, 0] - x64) <= 1e-5 * rmax), "x_ref"
-    assert np.all(np.abs(p[:, 1] - y64) <= 1e-5 * rmax), "y_ref"
+    pscale = np.maximum(np.hypot(x64, y64), HOLE_RADIUS_MM)
+    tscale = np.hypot(p64[:, 3], p64[:, 4])
+    assert np.all(np.abs(p[:, 0] - x64) <= 1e-5 * pscale), "x_ref"
+    assert np.all(np.abs(p[:, 1] - y64) <= 1e-5 * pscale), "y_ref"
     zscale = np.maximum(np.abs(plane_z[first]), np.abs(plane_z[last])).astype(np.float64)
     assert np.all(np.abs(p[:, 2] - p64[:, 2]) <= 1e-5 * zscale), "z_ref"
     assert np.all(np.abs(p[:, 3] - p64[:, 3]) <= 1e-5 * tscale), "tx"
