@@ -40,7 +40,9 @@
  *       d_status[7]             largest seed-candidate count of one plane step
  *                               on the large-event path (its pool per workgroup
  *                               is min(2^23, max(2^16, 16 * max_clusters /
- *                               max_events)) entries; beyond it: overflow)
+ *                               max_events)) entries; a step with more
+ *                               candidates is seeded in key ranges, each as
+ *                               large as the pool: same result, more passes)
  *       d_status[8 + e]         flags of event e (VELO_EV_*)
  *     so d_status holds VELO_STATUS_WORDS(n_events) int32.  On overflow every
  *     offset array is still complete and exact; element arrays are written only
@@ -134,6 +136,17 @@ int velo_set_validate(velo_ctx* ctx, int32_t on);
  * larger events lays the workspace out again even when the counts fit (every
  * earlier capacity is kept). */
 int velo_reserve(velo_ctx* ctx, int32_t max_events, int64_t max_pixels, int64_t max_clusters);
+
+/* Seed-candidate pool of each workgroup of the large-event finder: at most
+ * `entries` candidates of a plane step are held at once (1 <= entries <= the
+ * reserved pool, d_status[7]'s description gives its size; 0 = all of it).  A
+ * step with more candidates is seeded in ranges of the claiming key (q, h0),
+ * each range claimed before the next is enumerated -- the greedy claiming
+ * accepts in key order, so the tracks never depend on the pool; smaller pools
+ * take more passes over the step.  The overflow remains only if more
+ * candidates than the pool holds share one key (q, h0).  velo_reserve resets
+ * the pool to all of the reservation. */
+int velo_set_large_pool(velo_ctx* ctx, int64_t entries);
 
 /* Pixel clustering (connected components, 8-neighbourhood).
  *   in : d_pix_off[n_events*26+1] int32, d_pix_id[...] uint32

@@ -110,7 +110,8 @@ struct Work {
     float* p_q;
     int32_t* p_h;         // [entry][3] staged positions
     uint8_t* p_alive;
-    int64_t pool_cap;     // entries per block
+    int64_t pool_cap;     // entries per block (its stride in the pool)
+    int64_t pool_use;     // entries a block fills before seeding a step in key ranges (<= pool_cap)
     int32_t n_large_blocks;
     // cluster kernel global path scratch, per pixel
     int32_t* g_par;

@@ -219,7 +219,7 @@ struct GlobalStore {
     __device__ uint64_t* wkey64() { return w->g_slota + s->cb[seed_k]; }
     __device__ uint32_t* wtmp() { return w->g_slotb + s->cb[seed_k]; }
     __device__ int cap_tracks() const { return cap_t; }
-    __device__ int cap_cand() const { return (int)w->pool_cap; }
+    __device__ int cap_cand() const { return (int)w->pool_use; }
     int dbase = 0, dn = 0;
     int32_t* cell = nullptr;  // this workgroup's grid cell starts (plane-major)
     __device__ const int32_t* cells(int j) const { return cell + (int64_t)j * (kCells + 1); }
@@ -229,6 +229,7 @@ struct GlobalStore {
     static constexpr int kLutShift = 4;
     uint16_t (*luts)[kLutLarge + 1] = nullptr;  // LDS
     __device__ uint16_t* lut(int sl) { return luts[sl]; }
+    uint32_t* hist = nullptr;  // LDS histogram of the key-range seeding
 };
 
 // ---------------------------------------------------------------- windows
@@ -587,13 +588,28 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
     }
 }
 
+// A pass of the seeding of one plane step restricted to a range of candidate
+// keys (large-event path).  The key is the claiming order's first part, (q,
+// h0's plane-local index), as one 64-bit integer: q >= 0, so its bit pattern
+// orders like its value.  mode 1 counts the keys in [lo, hi] into hist (bin =
+// (key - lo) >> shift); mode 2 stores the candidates with keys in [lo, hi] from
+// pool entry `base` on.
+struct SeedRange {
+    int mode;
+    uint64_t lo, hi;
+    int shift;
+    uint32_t* hist;
+    int base;
+};
+
 // T2 candidate enumeration, load-balanced over (h0, h2) pairs: (A) every
 // unused h0 gets its azimuth window on plane k+2 (up to two position ranges);
 // (B) a block scan of the window sizes; (C) the pairs are dealt out evenly and
 // each surviving pair searches plane k+1 for its middle hit.  Returns false
-// (uniformly) on candidate overflow.
+// (uniformly) on candidate overflow.  rg (large-event path only): a pass
+// restricted to a key range; null: every candidate, stored from entry 0.
 template <int kT, class S>
-__device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
+__device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange* rg = nullptr) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
@@ -699,7 +715,19 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
             const float dy = y1 - ey;
             const float q = dx * dx + dy * dy;
             if (!(q <= p.s_max)) return;
-            const int c = atomicAdd(&sc.n_cand, 1);
+            int base = 0;
+            if constexpr (S::kLarge) {
+                if (rg) {
+                    const uint64_t key = ((uint64_t)__float_as_uint(q) << 32) | (uint32_t)st.L(s0, i0);
+                    if (key < rg->lo || key > rg->hi) return;
+                    if (rg->mode == 1) {
+                        atomicAdd(rg->hist + (int)((key - rg->lo) >> rg->shift), 1u);
+                        return;
+                    }
+                    base = rg->base;
+                }
+            }
+            const int c = base + atomicAdd(&sc.n_cand, 1);
             if (c < cap) {
                 st.cq(c) = q;
                 st.set_cp(c, i0, i1, i2);
@@ -724,6 +752,7 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k) {
     }
     __syncthreads();
     if constexpr (S::kLarge) {
+        if (rg) return rg->base + sc.n_cand <= cap;
         if (threadIdx.x == 0 && a.status) atomicMax(a.status + ST_MAXCAND, sc.n_cand);
     }
     return sc.n_cand <= cap;
@@ -760,7 +789,7 @@ __device__ __forceinline__ bool group_or(int v) {
 // candidates fit it).  Only the slots of hits that some candidate uses are
 // read, so only those are cleared.
 template <int kG, int kT, class S>
-__device__ void claim_rounds(S& st, int k, int nc) {
+__device__ void claim_rounds(S& st, int k, int c0, int nc) {
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     uint64_t* A0 = st.slotA(0);
     uint64_t* A1 = st.slotA(1);
@@ -768,7 +797,7 @@ __device__ void claim_rounds(S& st, int k, int nc) {
     uint32_t* B0 = st.slotB(0);
     uint32_t* B1 = st.slotB(1);
     uint32_t* B2 = st.slotB(2);
-    for (int c = threadIdx.x; c < nc; c += kG) {
+    for (int c = c0 + threadIdx.x; c < nc; c += kG) {
         const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
         A0[i0] = ~0ull; A1[i1] = ~0ull; A2[i2] = ~0ull;
         B0[i0] = ~0u; B1[i1] = ~0u; B2[i2] = ~0u;
@@ -781,7 +810,7 @@ __device__ void claim_rounds(S& st, int k, int nc) {
         return ((uint32_t)st.L(s1, st.cp(c, 1)) << 16) | (uint32_t)st.L(s2, st.cp(c, 2));
     };
     while (true) {
-        for (int c = threadIdx.x; c < nc; c += kG) {
+        for (int c = c0 + threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const uint64_t kA = keyA(c);
             atomicMin((unsigned long long*)(A0 + st.cp(c, 0)), kA);
@@ -791,7 +820,7 @@ __device__ void claim_rounds(S& st, int k, int nc) {
         group_sync<kG, kT>();
         // per hit: among the candidates holding the smallest (q, h0) there,
         // the smallest (h1, h2) -- the per-hit minimum of the full key
-        for (int c = threadIdx.x; c < nc; c += kG) {
+        for (int c = c0 + threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             const uint64_t kA = keyA(c);
@@ -801,7 +830,7 @@ __device__ void claim_rounds(S& st, int k, int nc) {
             if (A2[i2] == kA) atomicMin(B2 + i2, kB);
         }
         group_sync<kG, kT>();
-        for (int c = threadIdx.x; c < nc; c += kG) {
+        for (int c = c0 + threadIdx.x; c < nc; c += kG) {
             if (st.calive(c) != 1) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
             const uint64_t kA = keyA(c);
@@ -815,7 +844,7 @@ __device__ void claim_rounds(S& st, int k, int nc) {
         }
         group_sync<kG, kT>();
         int any = 0;
-        for (int c = threadIdx.x; c < nc; c += kG) {
+        for (int c = c0 + threadIdx.x; c < nc; c += kG) {
             const uint8_t al = st.calive(c);
             if (al != 1 && al != 2) continue;
             const int i0 = st.cp(c, 0), i1 = st.cp(c, 1), i2 = st.cp(c, 2);
@@ -833,14 +862,14 @@ __device__ void claim_rounds(S& st, int k, int nc) {
     }
 }
 
+// Claiming of the candidates [c0, c1) (by the first wave alone when they fit it).
 template <int kT, class S>
-__device__ void claim_seeds(S& st, const FindArgs&, int k) {
-    const int nc = st.s->n_cand;
-    if (kT > kWave && nc <= kWave) {
-        if (threadIdx.x < kWave) claim_rounds<kWave, kT>(st, k, nc);
+__device__ void claim_seeds(S& st, const FindArgs&, int k, int c0, int c1) {
+    if (kT > kWave && c1 - c0 <= kWave) {
+        if (threadIdx.x < kWave) claim_rounds<kWave, kT>(st, k, c0, c1);
         __syncthreads();
     } else {
-        claim_rounds<kT, kT>(st, k, nc);
+        claim_rounds<kT, kT>(st, k, c0, c1);
     }
 }
 
@@ -1064,10 +1093,9 @@ __device__ __forceinline__ void seed_features(S& st, const Params& p, int k, int
 // with the weights read from an LDS copy as uniform operands.  A candidate
 // whose logit exceeds the threshold dies.
 template <int kT, class S>
-__device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __restrict__ W) {
+__device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __restrict__ W, int cb0, int nc) {
     Scalars& sc = *st.s;
     const Params& p = a.p;
-    const int nc = sc.n_cand;
     const int s0 = k % kRing, s1 = (k + 1) % kRing, s2 = (k + 2) % kRing;
     const float fn[4] = {(float)k, (float)(sc.cb[k + 1] - sc.cb[k]), (float)(sc.cb[k + 2] - sc.cb[k + 1]),
                          (float)(sc.cb[k + 3] - sc.cb[k + 2])};
@@ -1082,11 +1110,11 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __rest
         }
     };
     bool per_lane = false;
-    if constexpr (S::kLarge) per_lane = on && nc >= kT / 4;
+    if constexpr (S::kLarge) per_lane = on && nc - cb0 >= kT / 4;
     if (per_lane) {
         if constexpr (S::kLarge) {
             const float* sw = st.seedw;
-            for (int c = threadIdx.x; c < nc; c += kT) {
+            for (int c = cb0 + threadIdx.x; c < nc; c += kT) {
                 float f[kSeedIn];
                 int i0, i1, i2;
                 seed_features(st, p, k, c, fn, f, &i0, &i1, &i2);
@@ -1126,7 +1154,7 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __rest
         // this group's 32 activations of each layer, broadcast through LDS
         float* b1 = st.bcast() + (threadIdx.x / kL) * kSeedH;
         float* b2 = b1 + kGroups * kSeedH;
-        for (int c0 = 0; c0 < nc; c0 += kGroups) {
+        for (int c0 = cb0; c0 < nc; c0 += kGroups) {
             const int c = c0 + (int)threadIdx.x / kL;
             const bool valid = c < nc;
             // idle groups take a valid candidate and still join the broadcasts
@@ -1168,6 +1196,104 @@ __device__ void seed_filter(S& st, const FindArgs& a, int k, const float* __rest
     __syncthreads();
 }
 
+// Seeding of a plane step whose candidates exceed the pool (large-event path):
+// the candidates are taken in ascending ranges of the key (q, h0), each range
+// as large as the pool holds -- a counting pass into a histogram of the keys
+// left finds its upper end, a second pass stores it -- and each range is
+// claimed before the next is enumerated.  The greedy claiming accepts in key
+// order and a candidate with a taken hit is never accepted, so claiming range
+// by range, skipping the hits earlier ranges took, accepts exactly what one
+// pass over all candidates accepts.  The winners of every range wait in the
+// claim words of planes k, k+1, k+2 (idle while plane k seeds: forwarding onto
+// plane k is done and downstream completion starts at k+3; at most one winner
+// per h0, so they fit), then go to the front of the pool (q, hits; state 3),
+// where create_tracks finds them, and the claim words are cleared again.
+// Returns false only when more candidates than the pool holds share one key.
+constexpr int kRangeBins = 1024;
+
+template <int kT, bool kSeed, class S>
+__device__ bool seed_ranges(S& st, const FindArgs& a, int k, const float* __restrict__ seed_net) {
+    Scalars& sc = *st.s;
+    const int cap = st.cap_cand();
+    uint32_t* hist = st.hist;
+    int32_t* wq = st.claimT(sc.cb[k]);        // q bits of winner j
+    int32_t* wa = st.claimT(sc.cb[k + 1]);    // h0 | h1 << 16 (staged positions)
+    int32_t* wb = st.claimT(sc.cb[k + 2]);    // h2
+    const uint64_t kmax = ((uint64_t)__float_as_uint(a.p.s_max) << 32) | 0xffffffffull;
+    uint64_t lo = 0;
+    if (threadIdx.x == 0) sc.n_acc = 0;  // winners so far
+    while (true) {
+        // upper end of the range: the largest bin boundary whose keys fit the pool
+        uint64_t top = kmax, hi = kmax;
+        while (true) {
+            int shift = 0;
+            while (((top - lo) >> shift) >= (uint64_t)kRangeBins) ++shift;
+            for (int b = threadIdx.x; b < kRangeBins; b += kT) hist[b] = 0;
+            __syncthreads();
+            const SeedRange rc{1, lo, top, shift, hist, 0};
+            enumerate_seeds<kT>(st, a, k, &rc);
+            // inclusive prefix sums over the bins (one thread: 1024 bins, rare path)
+            if (threadIdx.x == 0) {
+                uint32_t run = 0;
+                int last = -1;
+                for (int b = 0; b < kRangeBins; ++b) {
+                    run += hist[b];
+                    if (run <= (uint32_t)cap) last = b;
+                }
+                sc.wsum[0] = last;
+                sc.wsum[1] = run <= (uint32_t)cap ? 1 : 0;
+            }
+            __syncthreads();
+            const int last = sc.wsum[0];
+            const bool all = sc.wsum[1] != 0;
+            __syncthreads();
+            if (all) { hi = top; break; }
+            if (last >= 0) { hi = lo + (((uint64_t)(last + 1)) << shift) - 1; break; }
+            if (shift == 0) return false;  // one key alone exceeds the pool
+            top = lo + ((uint64_t)1 << shift) - 1;  // the first bin: split it finer
+        }
+        // store and claim the range [lo, hi]
+        if (threadIdx.x == 0) sc.n_cand = 0;
+        __syncthreads();
+        const SeedRange rs{2, lo, hi, 0, nullptr, 0};
+        if (!enumerate_seeds<kT>(st, a, k, &rs)) return false;
+        const int nc = sc.n_cand;
+        if (nc > 0) {
+            if constexpr (kSeed) seed_filter<kT>(st, a, k, seed_net, 0, nc);
+            claim_seeds<kT>(st, a, k, 0, nc);
+            for (int c = threadIdx.x; c < nc; c += kT) {
+                if (st.calive(c) != 3) continue;
+                const int j = atomicAdd(&sc.n_acc, 1);
+                wq[j] = (int32_t)__float_as_uint(st.cq(c));
+                wa[j] = st.cp(c, 0) | (st.cp(c, 1) << 16);
+                wb[j] = st.cp(c, 2);
+            }
+            __syncthreads();
+        }
+        if (hi >= kmax) break;
+        lo = hi + 1;
+    }
+    // the winners to the front of the pool (fewer than its physical size,
+    // which is at least 2^16 entries: one winner per h0 at most), claim words clear
+    const int nw = sc.n_acc;
+    for (int j = threadIdx.x; j < nw; j += kT) {
+        const uint32_t va = (uint32_t)wa[j];
+        st.cq(j) = __uint_as_float((uint32_t)wq[j]);
+        st.set_cp(j, (int)(va & 0xffffu), (int)(va >> 16), wb[j]);
+        st.calive(j) = 3;
+        wq[j] = kIntMax;
+        wa[j] = kIntMax;
+        wb[j] = kIntMax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc.n_cand = nw;
+        sc.n_acc = 0;
+    }
+    __syncthreads();
+    return true;
+}
+
 // Whole event.  Returns false when a capacity was too small (LDS tile: redo on
 // the large path; large path: overflow); on true the candidates are final.
 template <int kT, bool kSeed, class S>
@@ -1198,12 +1324,19 @@ __device__ bool find_event(S& st, const FindArgs& a, int e, const float* __restr
         PHASE(1);
         if (k <= kPlanes - 3) {
             st.seed_k = k;
-            if (!enumerate_seeds<kT>(st, a, k)) return false;
-            PHASE(2);
+            if (enumerate_seeds<kT>(st, a, k)) {
+                PHASE(2);
+                if (sc.n_cand > 0) {
+                    if constexpr (kSeed) seed_filter<kT>(st, a, k, seed_net, 0, sc.n_cand);
+                    claim_seeds<kT>(st, a, k, 0, sc.n_cand);
+                    PHASE(3);
+                }
+            } else if constexpr (S::kLarge) {
+                if (!seed_ranges<kT, kSeed>(st, a, k, seed_net)) return false;
+            } else {
+                return false;  // the larger tile or the large path redoes the event
+            }
             if (sc.n_cand > 0) {
-                if constexpr (kSeed) seed_filter<kT>(st, a, k, seed_net);
-                claim_seeds<kT>(st, a, k);
-                PHASE(3);
                 if (!create_tracks<kT>(st, a, k)) return false;
                 PHASE(4);
             }
@@ -1268,10 +1401,12 @@ template <int kT, bool kSeed>
 __global__ __launch_bounds__(kT) void k_find_large(FindArgs a, const float* __restrict__ seed_net) {
     __shared__ Scalars sc;
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
+    __shared__ uint32_t hist[kRangeBins];
     __shared__ __align__(16) float seedw[kSeed ? kSeedFloats : 1];
     __shared__ float seedh[kSeed ? kSeedH * kT : 1];
     GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
     st.luts = luts;
+    st.hist = hist;
     st.seedh = seedh;
     if constexpr (kSeed) {
         // the seed network with its weight matrices back in [unit][input] rows

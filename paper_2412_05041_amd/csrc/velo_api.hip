@@ -47,6 +47,7 @@ struct velo_ctx {
     Params p{};
     int validate = 0;
     int threads = 256, tile = 1;
+    int64_t pool_limit = 0;  // velo_set_large_pool (0: the reserved pool)
     Work w{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -170,6 +171,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, in
     // workgroups as a pool budget of 8 entries per cluster allows (at most 2
     // per CU, at least 1)
     w.pool_cap = std::max(pool_entries(E, C), min_pool);
+    w.pool_use = w.pool_cap;
     const int64_t budget = std::max<int64_t>(1 << 20, std::min<int64_t>(int64_t(1) << 29, 8 * C));
     w.n_large_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2 * std::max(n_cu, 1), budget / w.pool_cap));
     w.g_cell = carve<int32_t>(cur, kCellWords * w.n_large_blocks);
@@ -512,8 +514,14 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
     // covers the counts but was laid out for smaller events is laid out again
     const int64_t want_pool = pool_entries(std::max(max_events, 1), std::max<int64_t>(max_clusters, 1));
     if (c->ws && max_events <= c->w.cap_events && max_pixels <= c->w.cap_pixels &&
-        max_clusters <= c->w.cap_clusters && want_pool <= c->w.pool_cap)
+        max_clusters <= c->w.cap_clusters && want_pool <= c->w.pool_cap) {
+        if (c->w.pool_use != c->w.pool_cap) {  // a pool limit ends with any reservation
+            c->w.pool_use = c->w.pool_cap;
+            c->pool_limit = 0;
+            c->version++;
+        }
         return VELO_OK;
+    }
     int32_t E = std::max(max_events, 1);
     int64_t P = std::max<int64_t>(max_pixels, 1), C = std::max<int64_t>(max_clusters, 1), min_pool = want_pool;
     if (c->ws) {  // keep what the old reservation covered
@@ -536,6 +544,17 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
     c->w = w;
     c->ws = base;
     c->ws_bytes = bytes;
+    c->pool_limit = 0;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_set_large_pool(velo_ctx* c, int64_t entries) {
+    if (int rc = check_ctx(c)) return rc;
+    if (entries < 0 || entries > c->w.pool_cap)
+        return fail(VELO_ERR_ARG, "pool entries must be 0..%lld (the reserved pool)", (long long)c->w.pool_cap);
+    c->w.pool_use = entries ? entries : c->w.pool_cap;
+    c->pool_limit = entries;
     c->version++;
     return VELO_OK;
 }

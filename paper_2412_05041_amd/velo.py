@@ -53,6 +53,7 @@ _SIGS = {
     "velo_pipeline": [C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_int64] + [C.c_void_p] * 7 +
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
+    "velo_set_large_pool": [C.c_void_p, C.c_int64],
     "velo_get_launch": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_autotune": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                       C.c_char_p, C.c_void_p, C.c_void_p],
@@ -161,6 +162,9 @@ class Velo:
     def reserve(self, max_events: int, max_pixels: int, max_clusters: int | None = None):
         _check(lib().velo_reserve(self.h, int(max_events), int(max_pixels),
                                   int(max_pixels if max_clusters is None else max_clusters)))
+
+    def set_large_pool(self, entries: int):
+        _check(lib().velo_set_large_pool(self.h, int(entries)))
 
     def set_launch(self, threads: int, tile: int):
         _check(lib().velo_set_launch(self.h, threads, tile))
