@@ -36,10 +36,16 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
-    lib = SAN_LIB if sanitize else LIB
+# The finder with per-phase wall-clock counters (a diagnostic build; slower).
+PHASE_LIB = os.path.join(HERE, "libvelo_phase.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False, phase_timing: bool = False) -> str:
+    lib = SAN_LIB if sanitize else (PHASE_LIB if phase_timing else LIB)
     tmp = lib + ".tmp%d" % os.getpid()
     flags = list(FLAGS)
+    if phase_timing:
+        flags.append("-DVELO_PHASE_TIMING")
     if sanitize:
         flags[flags.index("-O3")] = "-O1"
         flags += SAN_HOST
@@ -63,4 +69,5 @@ def sanitizer_runtime() -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv,
+                phase_timing="--phase-timing" in sys.argv))

@@ -20,7 +20,6 @@ constexpr float kGridInv = 2.0f;
 constexpr float kGridOrg = 40.0f;
 constexpr int64_t kCellWords = (int64_t)26 * (kCells + 1) + kCells;  // per workgroup
 constexpr int kMaxLdsBlocksPerCu = 8;  // bound of the LDS-tile finder's grid
-constexpr int kLutSmall = 256;         // key buckets of an LDS-tile plane
 constexpr int kWave = 64;
 
 // Seed-level filter network (10 -> 32 -> 32 -> 1) as the finder reads it: the

@@ -46,39 +46,57 @@ constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kRing = 5;  // planes k .. k+4 in the window
 constexpr int kLutLarge = 4096;  // key buckets of a large-event plane
-constexpr int kLutCoarseBits = 6;
-constexpr int kLutCoarse = 1 << kLutCoarseBits;  // key buckets of the per-event coarse index
 constexpr float kKeysPerRad = 10430.378350470453f;  // 2^16 / (2 pi)
 
+// Phase timing (a diagnostic build, -DVELO_PHASE_TIMING): per finder pass
+// (0: first LDS tile, 1: second tile, 2: global memory) thread 0 of each
+// workgroup adds the wall-clock ticks of each phase of a plane step, after a
+// barrier: 0 plane load, 1 forwarding, 2 seed enumeration, 3 seed filter +
+// claiming, 4 track creation + downstream completion; then 5/6 downstream
+// completion steps on ring / non-ring planes, 7 ticks of the latter, 8
+// events, 9 ticks of whole events.
 #ifdef VELO_PHASE_TIMING
-__device__ unsigned long long g_phase[8];
-#define PHASE_T0() uint64_t ph_t = wall_clock64()
+constexpr int kPhaseSlots = 12;
+__device__ unsigned long long g_phase[3][kPhaseSlots];
+__device__ __forceinline__ int phase_pass(const FindArgs& a) {
+    return a.q_in == a.w.order ? 0 : (a.q_in == a.w.large ? 1 : 2);
+}
+#define PHASE_T0() uint64_t ph_t = wall_clock64(), ph_t0 = ph_t
 #define PHASE(i)                                                        \
     do {                                                                \
         __syncthreads();                                                \
         if (threadIdx.x == 0) {                                         \
             const uint64_t now = wall_clock64();                        \
-            atomicAdd(&g_phase[i], (unsigned long long)(now - ph_t));   \
+            atomicAdd(&g_phase[phase_pass(a)][i], (unsigned long long)(now - ph_t)); \
             ph_t = now;                                                 \
         }                                                               \
     } while (0)
 #define PCOUNT(i, v)                                                    \
     do {                                                                \
-        if (threadIdx.x == 0) atomicAdd(&g_phase[i], (unsigned long long)(v)); \
+        if (threadIdx.x == 0) atomicAdd(&g_phase[phase_pass(a)][i], (unsigned long long)(v)); \
     } while (0)
 #define PCLOCK() wall_clock64()
+#define PHASE_END()                                                     \
+    do {                                                                \
+        PCOUNT(8, 1);                                                   \
+        PCOUNT(9, wall_clock64() - ph_t0);                              \
+    } while (0)
 #else
 #define PHASE_T0() (void)0
 #define PHASE(i) (void)0
 #define PCOUNT(i, v) (void)0
 #define PCLOCK() 0ull
+#define PHASE_END() (void)0
 #endif
 
 // ---------------------------------------------------------------- storage
 // Accessors hide where a workgroup keeps its per-event state: the LDS tile
 // (normal events) or global scratch (large events).
 
-template <int kP, int kT, int kC>
+// An LDS tile: plane capacity kP, tracks kT, seed candidates per step kC;
+// 2^kLB key buckets in the index of a ring plane, 2^kCB in the coarse index
+// every plane of the event keeps.
+template <int kP, int kT, int kC, int kLB, int kCB>
 struct Tile {
     float wx[kRing][kP];
     float wy[kRing][kP];
@@ -97,8 +115,8 @@ struct Tile {
     float cq[kC];
     uint16_t cp[kC][3];
     uint8_t calive[kC];
-    uint16_t lut[kRing][kLutSmall + 1];  // first position of each key bucket
-    uint16_t clut[kPlanes][kLutCoarse + 1];  // coarse bucket index of every plane of the event
+    uint16_t lut[kRing][(1 << kLB) + 1];     // first position of each key bucket
+    uint16_t clut[kPlanes][(1 << kCB) + 1];  // coarse bucket index of every plane of the event
 };
 
 struct Scalars {
@@ -111,10 +129,10 @@ struct Scalars {
     int64_t cb[kPlanes + 1]; // global cluster offsets of the event's planes
 };
 
-template <int kP, int kT, int kC>
+template <int kP, int kT, int kC, int kLB, int kCB>
 struct LdsStore {
     static constexpr bool kLarge = false;
-    Tile<kP, kT, kC>* t;
+    Tile<kP, kT, kC, kLB, kCB>* t;
     Scalars* s;
     int64_t slot0;
     int seed_k = 0;
@@ -168,8 +186,10 @@ struct LdsStore {
     __device__ uint32_t* wtmp() { return &t->slotb[2][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
-    static constexpr int kLutN = kLutSmall;
-    static constexpr int kLutShift = 8;
+    static constexpr int kLutN = 1 << kLB;
+    static constexpr int kLutShift = kKeyBits - kLB;
+    static constexpr int kCoarseN = 1 << kCB;
+    static constexpr int kCoarseShift = kKeyBits - kCB;
     __device__ uint16_t* lut(int sl) { return t->lut[sl]; }
 };
 
@@ -457,7 +477,7 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
         t->wid[sl][i] = (uint16_t)id;
         t->claim[i] = kIntMax;
         lut_entries<kShift, kN>(lut, i, n, key, kprev);
-        lut_entries<16 - kLutCoarseBits, kLutCoarse>(clut, i, n, key, kprev);
+        lut_entries<S::kCoarseShift, S::kCoarseN>(clut, i, n, key, kprev);
     };
 #pragma unroll
     for (int r = 0; r < kPF; ++r) {
@@ -469,7 +489,7 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
     if (n == 0)
         for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
     if (n == 0)
-        for (int b = threadIdx.x; b <= kLutCoarse; b += kT) clut[b] = 0;
+        for (int b = threadIdx.x; b <= S::kCoarseN; b += kT) clut[b] = 0;
     if (threadIdx.x == 0) {
         sc.wg[sl] = g;
         sc.wn[sl] = n;
@@ -1027,7 +1047,7 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
                 // its coarse bucket index, used flags in LDS
                 const uint16_t* clut = st.t->clut[j];
                 open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
-                                          [&](int v) { return lower_lut<16 - kLutCoarseBits>(clut, key, nj, v); }, key,
+                                          [&](int v) { return lower_lut<S::kCoarseShift>(clut, key, nj, v); }, key,
                                           [&](int i) { return st.UP(j, i); }, [&](int i) { st.set_UP(j, i); },
                                           xf, yf, idf, g);
             }
@@ -1343,6 +1363,7 @@ __device__ bool find_event(S& st, const FindArgs& a, int e, const float* __restr
         }
     }
     const int nt = sc.n_tracks;
+    PHASE_END();
     if constexpr (!S::kLarge) {
         for (int t = threadIdx.x; t < nt; t += kT) a.w.cmask[st.slot0 + t] = st.tmask(t);
     }
@@ -1359,11 +1380,18 @@ __device__ __forceinline__ void write_empty(const FindArgs& a, int e, int flag) 
 // the plain finder keeps its register allocation and occupancy).
 // seed_net: the seed network (null: none), a separate read-only argument so that
 // its uniform weights load through the scalar cache.
-template <int kT, int kP, int kTr, int kC, bool kSeed>
-__global__ __launch_bounds__(kT, kT >= 512 ? 4 : 1) void k_find_lds(FindArgs a, const float* __restrict__ seed_net) {
-    __shared__ Tile<kP, kTr, kC> tile;
+// Waves per SIMD the register allocation must allow: four 256-thread
+// workgroups of the first tile share a CU (their LDS fits four times), and
+// 512-thread ones need four waves per SIMD to run one workgroup per CU.
+template <int kT, int kP>
+constexpr int find_waves_per_eu() { return kT >= 512 ? 4 : (kT == 256 && kP <= 256 ? 4 : 1); }
+
+template <int kT, int kP, int kTr, int kC, int kLB, int kCB, bool kSeed>
+__global__ __launch_bounds__(kT, (find_waves_per_eu<kT, kP>())) void k_find_lds(FindArgs a,
+                                                                               const float* __restrict__ seed_net) {
+    __shared__ Tile<kP, kTr, kC, kLB, kCB> tile;
     __shared__ Scalars sc;
-    LdsStore<kP, kTr, kC> st{&tile, &sc, 0};
+    LdsStore<kP, kTr, kC, kLB, kCB> st{&tile, &sc, 0};
     while (true) {
         if (threadIdx.x == 0) {
             const int n = a.q_count < 0 ? a.n_events : a.w.counters[a.q_count];
@@ -1526,34 +1554,37 @@ __global__ __launch_bounds__(256) void k_accept(FindArgs a) {
 
 bool seed_variant(const FindArgs& a) { return a.seed_net != nullptr || a.seed_feat != nullptr; }
 
-template <int kT, int kP, int kTr, int kC>
+template <int kT, int kP, int kTr, int kC, int kLB, int kCB>
 hipError_t launch_lds(const FindArgs& a, int grid, hipStream_t s) {
     if (seed_variant(a))
-        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, true>), dim3(grid), dim3(kT), 0, s, a, a.seed_net);
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, kLB, kCB, true>), dim3(grid), dim3(kT), 0, s, a, a.seed_net);
     else
-        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, false>), dim3(grid), dim3(kT), 0, s, a, nullptr);
+        hipLaunchKernelGGL((k_find_lds<kT, kP, kTr, kC, kLB, kCB, false>), dim3(grid), dim3(kT), 0, s, a, nullptr);
     return hipGetLastError();
 }
 
-template <int kT, int kP, int kTr, int kC>
+template <int kT, int kP, int kTr, int kC, int kLB, int kCB>
 int occ_lds(bool seed) {
     int n = 0;
-    const hipError_t e = seed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, true>, kT, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, false>, kT, 0);
+    const hipError_t e =
+        seed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, kLB, kCB, true>, kT, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_find_lds<kT, kP, kTr, kC, kLB, kCB, false>, kT, 0);
     return e == hipSuccess ? n : 1;
 }
 
 }  // namespace
 
-// Tile shapes: (plane capacity, tracks, seed candidates per step).
-#define VELO_TILES(X, T)               \
-    X(T, 0, 256, 320, 384)             \
-    X(T, 1, 512, 640, 640)             \
-    X(T, 2, 1024, 1024, 1024)
+// Tile shapes: (plane capacity, tracks, seed candidates per step, key-index
+// bits of a ring plane, of the per-event coarse index).  The first tile is
+// sized so that four 256-thread workgroups fit a CU's 160 KB of LDS.
+#define VELO_TILES(X, T)                   \
+    X(T, 0, 256, 304, 336, 7, 5)           \
+    X(T, 1, 512, 640, 640, 8, 6)           \
+    X(T, 2, 1024, 1024, 1024, 8, 6)
 
 static hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int grid, hipStream_t s) {
-#define VELO_CASE(T, L, P, TR, C) \
-    case T * 4 + L: return launch_lds<T, P, TR, C>(a, grid, s);
+#define VELO_CASE(T, L, P, TR, C, LB, CB) \
+    case T * 4 + L: return launch_lds<T, P, TR, C, LB, CB>(a, grid, s);
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
@@ -1565,8 +1596,8 @@ static hipError_t launch_find_lds(const FindArgs& a, int threads, int tile, int 
 }
 
 int find_blocks_per_cu(int threads, int tile, bool seed) {
-#define VELO_CASE(T, L, P, TR, C) \
-    case T * 4 + L: return occ_lds<T, P, TR, C>(seed);
+#define VELO_CASE(T, L, P, TR, C, LB, CB) \
+    case T * 4 + L: return occ_lds<T, P, TR, C, LB, CB>(seed);
     switch (threads * 4 + tile) {
         VELO_TILES(VELO_CASE, 64)
         VELO_TILES(VELO_CASE, 128)
@@ -1586,7 +1617,7 @@ static hipError_t launch_find_large(const FindArgs& a, hipStream_t s) {
 }
 
 int tile_planes(int tile) {
-#define VELO_CASE(T, L, P, TR, C) \
+#define VELO_CASE(T, L, P, TR, C, LB, CB) \
     case L: return P;
     switch (tile) {
         VELO_TILES(VELO_CASE, 0)
@@ -1623,10 +1654,11 @@ hipError_t launch_finder_large(FindArgs a, hipStream_t s) {
 }
 
 #ifdef VELO_PHASE_TIMING
+// out: 3 passes x 12 slots (see g_phase); reset clears them afterwards.
 extern "C" int velo_probe_phase(unsigned long long* out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 8) != hipSuccess) return -1;
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return -1;
     if (reset) {
-        unsigned long long z[8] = {};
+        unsigned long long z[3 * kPhaseSlots] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return -1;
     }
     return 0;
