@@ -222,7 +222,8 @@ def main():
 
     if args.mode == "learned":
         from paper_2412_05041_amd import learned
-        master, norm = learned.load_default_weights()
+        # the network trained on this generator's candidates where there is one
+        master, norm = learned.load_default_weights(learned.NOMINAL_WEIGHTS if w.ms_sigma > 0 else learned.WEIGHTS)
         cuts = dict(cuts, mode=1, logit_band=learned.DEFAULT_BAND)
     def new_context():
         c = velo.Velo(batch.plane_z, cuts, device=0)

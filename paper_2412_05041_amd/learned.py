@@ -3,13 +3,16 @@
 Everything numeric runs in libvelo's kernels (candidate finding, features, MLP
 forward/backward, Adam); this module only moves data and keeps score.
 
-Workload (the learned-filter configuration): candidates from the single-vertex
-generator (20 straight tracks per event, no scattering, no noise) found with
-loose windows (x3 on the default distances) and emitted with or without the
-chi2 cut; label 1 = ghost (< 70 % of the hits from one MC track).  The network
-(10 -> 32 -> 32 -> 1, BF16 weights/activations, FP32 accumulation) is trained
-with Adam on batches of 65536 candidates and compared with the plain chi2 cut
-on the same candidates of independent test events.
+Workloads: (1) the learned-filter configuration, candidates from the
+single-vertex generator (20 straight tracks per event, no scattering, no
+noise) found with loose windows (x3 on the default distances); (2) candidates
+of the nominal generator (pile-up, 1 mrad scattering, noise) found with the
+scattering cut set, ~0.6 % of them ghosts, ghosts weighted 4:1 in the loss.
+Every candidate is emitted with or without the chi2 cut; label 1 = ghost (< 70
+% of the hits from one MC track).  The network (10 -> 32 -> 32 -> 1, BF16
+weights/activations, FP32 accumulation) is trained with Adam on batches of
+65536 candidates and compared with the plain chi2 cut on the same candidates
+of independent test events.
 """
 from __future__ import annotations
 
@@ -25,6 +28,9 @@ from . import gen, metrics, velo
 HERE = os.path.dirname(os.path.abspath(__file__))
 CFG = os.path.join(HERE, "configs")
 WEIGHTS = os.path.join(CFG, "mlp_default.npz")
+# the network trained on candidates of the nominal generator (pile-up,
+# scattering, noise; the scattering cut set), ghosts weighted 4:1
+NOMINAL_WEIGHTS = os.path.join(CFG, "mlp_nominal.npz")
 DEFAULT_BAND = math.log(0.6 / 0.4)  # |sigmoid(z) - 0.5| < 0.1  <=>  |z| < ln(0.6/0.4)
 N_PARAM = 1441
 BATCH = 65536
@@ -44,8 +50,8 @@ def he_uniform(seed: int = 1004) -> np.ndarray:
     return w
 
 
-def load_default_weights():
-    d = np.load(WEIGHTS, allow_pickle=False)
+def load_default_weights(path: str = WEIGHTS):
+    d = np.load(path, allow_pickle=False)
     return d["master"].astype(np.float32), d["norm"].astype(np.float32)
 
 
