@@ -1,6 +1,6 @@
 // k_mlp.hip -- learned ghost filter: 10 -> 32 -> 32 -> 1 ReLU MLP on BF16 MFMA
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), its training gradient with a
-// fixed-order (deterministic) reduction, Adam, and the candidate features.
+// (FP32 accumulation), its training gradient with a fixed-order
+// (deterministic) reduction, Adam, and the candidate features.
 //
 // Orientation: samples run along the MFMA N dimension and the weights are the
 // A operand, so a layer's accumulator layout (lane l holds rows 4(l/16)+j,
@@ -8,6 +8,13 @@
 // leave registers in the forward pass.  Only the weight-gradient products,
 // whose reduction dimension is the sample, go through a small per-wave LDS
 // transpose.
+//
+// The products over the 32 hidden units (the second layer, and its transpose
+// in the gradient) are one gfx950 v_mfma_f32_16x16x32_bf16 each: a lane's
+// eight K slots hold the units 4g..4g+3 and 16+4g..16+4g+3 of the two 16-unit
+// accumulator tiles, in both operands -- a reduction index can be laid out in
+// any order the two operands share.  The products over 16 samples and over
+// the 10 inputs use v_mfma_f32_16x16x16_bf16.
 //
 // Rounding: weights, inputs and hidden activations are BF16 (round to nearest
 // even); biases are added in FP32 (they initialise the accumulator); the last
@@ -22,10 +29,22 @@ namespace velo {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// K = 32: the eight slots of a lane are (lo[0..3], hi[0..3]) in both operands.
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                  0, 0);
+}
+
+__device__ __forceinline__ bf16x8 cat(bf16x4 lo, bf16x4 hi) {
+    return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
 __device__ __forceinline__ short bf(float f) { return (short)f2bf(f); }
@@ -78,8 +97,7 @@ __device__ __forceinline__ void forward16(const Net& n, bf16x4 x, Fwd& f) {
     float part = 0.0f;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-        f32x4 acc = mfma16(n.a2[mt][0], f.h1[0], n.c2[mt]);
-        acc = mfma16(n.a2[mt][1], f.h1[1], acc);
+        const f32x4 acc = mfma32(cat(n.a2[mt][0], n.a2[mt][1]), cat(f.h1[0], f.h1[1]), n.c2[mt]);
         f.a2[mt] = acc;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -257,8 +275,7 @@ __global__ __launch_bounds__(kGradThreads) void k_mlp_grad(const float* master, 
         bf16x4 ga1[2];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-            f32x4 gh = mfma16(a2t[mt][0], ga2[0], f32x4{0, 0, 0, 0});
-            gh = mfma16(a2t[mt][1], ga2[1], gh);
+            const f32x4 gh = mfma32(cat(a2t[mt][0], a2t[mt][1]), cat(ga2[0], ga2[1]), f32x4{0, 0, 0, 0});
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float v = f.a1[mt][j] > 0.0f ? gh[j] : 0.0f;
