@@ -369,10 +369,19 @@ __global__ __launch_bounds__(1024) void k_scan_seg(ClusterArgs a) {
 }
 
 // Global numbering, centroid output and (fused pipeline) staging.
+// LDS of a staging wave, 4 KB: a segment of at most kCap clusters sorts in it
+// (keys, 16-bit positions, kSmallBuckets counters); a larger one keeps its
+// keys and positions in the per-pixel scratch and its kBuckets counters here.
+struct StageLds {
+    uint32_t w[kBuckets];
+    __device__ uint32_t* keys() { return w; }
+    __device__ uint16_t* pos() { return reinterpret_cast<uint16_t*>(w + kCap); }
+    __device__ uint32_t* hist_small() { return w + kCap + kCap / 2; }
+    static_assert(kCap + kCap / 2 + kSmallBuckets <= kBuckets, "the small layout fits");
+};
+
 __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
-    __shared__ uint32_t s_k[kCap];
-    __shared__ int32_t s_t[kCap];
-    __shared__ uint32_t s_hist[kBuckets];
+    __shared__ StageLds s_lds;
     const int seg = blockIdx.x;
     if (seg >= a.n_seg) return;
     const Work& w = a.w;
@@ -399,27 +408,26 @@ __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
     }
     if (!a.stage) return;
     if (m <= kCap) {
-        stage_segment<kSmallBuckets>(tx, ty, m, cb, s_k, s_t, s_hist, w);
+        stage_segment<kSmallBuckets>(tx, ty, m, cb, s_lds.keys(), s_lds.pos(), s_lds.hist_small(), w);
     } else {
-        stage_segment<kBuckets>(tx, ty, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0, s_hist, w);
+        stage_segment<kBuckets>(tx, ty, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0, s_lds.w, w);
     }
 }
 
 // Staging alone (velo_find_tracks on caller-provided clusters): one wave per segment.
 __global__ __launch_bounds__(kWave) void k_stage(StageArgs a) {
-    __shared__ uint32_t s_k[kCap];
-    __shared__ int32_t s_t[kCap];
-    __shared__ uint32_t s_hist[kBuckets];
+    __shared__ StageLds s_lds;
     const int seg = blockIdx.x;
     if (seg >= a.n_seg) return;
     const int64_t cb = a.clu_off[seg];
     const int m = a.clu_off[seg + 1] - (int)cb;
     if (m <= 0 || cb + m > a.w.cap_clusters) return;  // the finder flags such events
     if (m <= kCap) {
-        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_k, s_t, s_hist, a.w);
+        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_lds.keys(), s_lds.pos(),
+                                     s_lds.hist_small(), a.w);
     } else {
         stage_segment<kBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, (uint32_t*)(a.w.g_par + cb), a.w.g_tmp + cb,
-                                s_hist, a.w);
+                                s_lds.w, a.w);
     }
 }
 

@@ -186,6 +186,7 @@ struct LdsStore {
     __device__ uint32_t* wtmp() { return &t->slotb[2][0]; }
     __device__ int cap_tracks() const { return kT; }
     __device__ int cap_cand() const { return kC; }
+    static constexpr int kPlaneCap = kP;
     static constexpr int kLutN = 1 << kLB;
     static constexpr int kLutShift = kKeyBits - kLB;
     static constexpr int kCoarseN = 1 << kCB;
@@ -195,6 +196,7 @@ struct LdsStore {
 
 struct GlobalStore {
     static constexpr bool kLarge = true;
+    static constexpr int kPlaneCap = 0;  // planes stay in global memory
     Scalars* s;
     const Work* w;
     int64_t slot0;   // first candidate slot of the event
@@ -370,6 +372,34 @@ __device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf,
         const int id = idf(i);
         if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
     });
+    return want;
+}
+
+// best_hit on a plane read from global memory through a bucket index: every
+// position of the buckets the key ranges touch is visited -- the bounds come
+// from the index alone, so the loads of one search do not wait for each other
+// -- and the key test inside keeps exactly the positions best_hit visits.
+template <int kShift, class KF, class UF, class XF, class YF, class IF>
+__device__ __forceinline__ int best_hit_buckets(const uint16_t* lut, KF key, UF used, XF xf, YF yf, IF idf, float ex,
+                                                float ey, const Params& p) {
+    int lo[2], hi[2];
+    const int nr = point_window(ex, ey, p.r_ext, lo, hi);
+    float bq = 0.0f;
+    int bid = kIntMax, want = -1;
+    for (int r = 0; r < nr; ++r) {
+        const int i0 = lut[lo[r] >> kShift], i1 = lut[(hi[r] >> kShift) + 1];
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
+            const int k = key(i);
+            const float dx = xf(i) - ex;
+            const float dy = yf(i) - ey;
+            if (k < lo[r] || k > hi[r] || used(i)) continue;
+            const float q = dx * dx + dy * dy;
+            if (!(q <= p.e_max)) continue;
+            const int id = idf(i);
+            if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+        }
+    }
     return want;
 }
 
@@ -897,9 +927,9 @@ __device__ void claim_seeds(S& st, const FindArgs&, int k, int c0, int c1) {
 // of kG threads (the workgroup, or its first wave when the tracks fit it).  The
 // plane is read through the accessors given (LDS ring or global staging).
 // Returns (uniformly over the group) whether any track was still open.
-template <int kG, int kT, class S, class LF, class KF, class UF, class SF, class XF, class YF, class IF>
-__device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, LF lower,
-                               KF key, UF used, SF set_used, XF xf, YF yf, IF idf, int64_t gbase) {
+template <int kG, int kT, class S, class SR, class SF, class XF, class YF, class IF>
+__device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, int n, int32_t* claimT, SR search,
+                               SF set_used, XF xf, YF yf, IF idf, int64_t gbase) {
     const Params& p = a.p;
     if constexpr (!S::kLarge) {
         for (int i = threadIdx.x; i < n; i += kG) claimT[i] = kIntMax;
@@ -915,8 +945,7 @@ __device__ bool complete_plane(S& st, const FindArgs& a, int j, int t0, int t1, 
             const float ex = st.dxb(t) + st.dtx(t) * d;
             const float ey = st.dyb(t) + st.dty(t) * d;
             if (n > 0) {
-                if constexpr (S::kLarge) want = best_hit_grid(a.w, st.cells(j), gbase, ex, ey, p);
-                else want = best_hit(lower, key, used, xf, yf, idf, n, ex, ey, p);
+                want = search(ex, ey);
                 if (want >= 0) atomicMin(claimT + want, t);
             }
         }
@@ -1022,11 +1051,15 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             const int nj = sc.wn[sl];
             const uint16_t* lut = st.lut(sl);
             auto key = [&](int i) { return st.K(sl, i); };
-            open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0),
-                                      [&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
-                                      [&](int i) { return st.U(sl, j, i); }, [&](int i) { st.set_U(sl, j, i); },
-                                      [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
-                                      [&](int i) { return st.L(sl, i); }, sc.wg[sl]);
+            auto xf = [&](int i) { return st.X(sl, i); };
+            auto yf = [&](int i) { return st.Y(sl, i); };
+            auto idf = [&](int i) { return st.L(sl, i); };
+            auto search = [&](float ex, float ey) {
+                return best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
+                                [&](int i) { return st.U(sl, j, i); }, xf, yf, idf, nj, ex, ey, a.p);
+            };
+            open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0), search,
+                                          [&](int i) { st.set_U(sl, j, i); }, xf, yf, idf, sc.wg[sl]);
             PCOUNT(5, 1);
         } else {
             const uint64_t tg = PCLOCK();
@@ -1038,18 +1071,19 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             auto yf = [&](int i) { return w.sy[g + i]; };
             auto idf = [&](int i) { return (int)(w.sid[g + i] - g); };
             if constexpr (S::kLarge) {
-                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
-                                          [&](int v) { return lower_key(key, nj, v); }, key,
-                                          [&](int i) { return w.used[g + i] != 0; }, [&](int i) { w.used[g + i] = 1; },
-                                          xf, yf, idf, g);
+                auto search = [&](float ex, float ey) { return best_hit_grid(w, st.cells(j), g, ex, ey, a.p); };
+                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g), search,
+                                              [&](int i) { w.used[g + i] = 1; }, xf, yf, idf, g);
             } else {
                 // a plane that has left the ring: hits from global staging through
                 // its coarse bucket index, used flags in LDS
                 const uint16_t* clut = st.t->clut[j];
-                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g),
-                                          [&](int v) { return lower_lut<S::kCoarseShift>(clut, key, nj, v); }, key,
-                                          [&](int i) { return st.UP(j, i); }, [&](int i) { st.set_UP(j, i); },
-                                          xf, yf, idf, g);
+                auto search = [&](float ex, float ey) {
+                    return best_hit_buckets<S::kCoarseShift>(clut, key, [&](int i) { return st.UP(j, i); }, xf, yf,
+                                                             idf, ex, ey, a.p);
+                };
+                open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g), search,
+                                              [&](int i) { st.set_UP(j, i); }, xf, yf, idf, g);
             }
             PCOUNT(6, 1);
             PCOUNT(7, PCLOCK() - tg);
@@ -1329,7 +1363,9 @@ __device__ bool find_event(S& st, const FindArgs& a, int e, const float* __restr
     }
     __syncthreads();
     PHASE_T0();
-    constexpr int kPF = kT >= 512 ? 1 : 2;
+    // hits per thread prefetched one plane ahead: as many as a full plane of
+    // the tile needs, at most two
+    constexpr int kPF = S::kLarge ? 1 : ((S::kPlaneCap + kT - 1) / kT > 2 ? 2 : (S::kPlaneCap + kT - 1) / kT);
     Prefetch pf;
     if constexpr (!S::kLarge) prefetch_plane<kT, kPF>(sc, a, kPlanes - 1, pf);
     for (int k = kPlanes - 1; k >= 0; --k) {

@@ -97,7 +97,8 @@ def test_large_events_three_calls_and_pipeline(name):
     cc = dict(clu_x=np_(c["clu_x"], n_clu), clu_y=np_(c["clu_y"], n_clu))
     p64 = assert_fit_close(par, tr, cc, b.plane_z, cuts(g["cuts"])["sigma"])
     idx = g["fit_sample"]["tracks"]
-    assert np.allclose(p64[idx, :7], np.array(g["fit_sample"]["par64"]), rtol=1e-12, atol=1e-9)
+    assert np.allclose(p64[idx, :7], np.array(g["fit_sample"]["par64"], np.float64).reshape(-1, 7), rtol=1e-12,
+                       atol=1e-9)
     bufs = v.pipeline_buffers(b.n_events, b.n_pix)
     v.pipeline(off, ids, bufs)
     torch.cuda.synchronize()
