@@ -53,15 +53,20 @@ enum : int { TRK_PLAIN = 1, TRK_LEARNED = 2, TRK_FALLBACK = 4, TRK_ACCEPT = 8 };
 enum : int { ST_SEVERITY = 0, ST_NCLU = 1, ST_NTRK = 2, ST_NHIT = 3, ST_NPIX = 4, ST_NLARGE = 5,
              ST_NFALLBACK = 6, ST_MAXCAND = 7 };
 
+// A staged hit: coordinates, global cluster index and azimuth key in one
+// 16-byte record, so that a hit is one vector load.
+struct __align__(16) Staged {
+    float x, y;
+    int32_t id;
+    uint32_t key;
+};
+
 // Device workspace (allocated by velo_reserve).  Per-cluster arrays are indexed
 // by global cluster index; per-candidate arrays by candidate slot, where the
 // candidates of event e occupy [clu_off[26 e], clu_off[26 e] + n_cand(e)).
 struct Work {
     // azimuth-sorted staging of each (event, plane): x, y, key, global cluster index
-    float* sx;
-    float* sy;
-    uint16_t* skey;
-    int32_t* sid;
+    struct Staged* stg;   // one 16-byte record per staged position
     uint8_t* used;        // per staged position: hit taken
     // large-event path: each plane's hits again in grid-cell order (x, y and
     // the staged position), and per workgroup the cell starts of all planes

@@ -125,10 +125,7 @@ __device__ void stage_segment(const float* cx, const float* cy, int m, int64_t g
             r += (ki < kj || (ki == kj && i < j)) ? 1 : 0;
         }
         const int64_t g = gbase + r;
-        w.sx[g] = cx[j];
-        w.sy[g] = cy[j];
-        w.skey[g] = (uint16_t)kj;
-        w.sid[g] = (int32_t)(gbase + j);
+        w.stg[g] = Staged{cx[j], cy[j], (int32_t)(gbase + j), kj};
         w.used[g] = 0;
     }
 }

@@ -206,11 +206,11 @@ struct GlobalStore {
     const float* seedw = nullptr;  // seed network in LDS, rows [unit][input] (seed variant)
     float* seedh = nullptr;        // per-thread first-layer activations in LDS, [unit][thread]
     __device__ float* bcast() { return seedh; }  // seed-filter broadcast scratch (>= 2 x 16 x 32 floats)
-    __device__ float X(int sl, int i) const { return w->sx[s->wg[sl] + i]; }
-    __device__ float Y(int sl, int i) const { return w->sy[s->wg[sl] + i]; }
-    __device__ int K(int sl, int i) const { return w->skey[s->wg[sl] + i]; }
-    __device__ int L(int sl, int i) const { return (int)(w->sid[s->wg[sl] + i] - s->wg[sl]); }
-    __device__ int64_t ID(int sl, int i) const { return w->sid[s->wg[sl] + i]; }
+    __device__ float X(int sl, int i) const { return w->stg[s->wg[sl] + i].x; }
+    __device__ float Y(int sl, int i) const { return w->stg[s->wg[sl] + i].y; }
+    __device__ int K(int sl, int i) const { return (int)w->stg[s->wg[sl] + i].key; }
+    __device__ int L(int sl, int i) const { return (int)(w->stg[s->wg[sl] + i].id - s->wg[sl]); }
+    __device__ int64_t ID(int sl, int i) const { return w->stg[s->wg[sl] + i].id; }
     __device__ bool U(int sl, int, int i) const { return w->used[s->wg[sl] + i] != 0; }
     __device__ void set_U(int sl, int, int i) { w->used[s->wg[sl] + i] = 1; }
     __device__ int32_t* claim(int sl) { return w->g_claim + s->wg[sl]; }
@@ -379,9 +379,9 @@ __device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf,
 // position of the buckets the key ranges touch is visited -- the bounds come
 // from the index alone, so the loads of one search do not wait for each other
 // -- and the key test inside keeps exactly the positions best_hit visits.
-template <int kShift, class KF, class UF, class XF, class YF, class IF>
-__device__ __forceinline__ int best_hit_buckets(const uint16_t* lut, KF key, UF used, XF xf, YF yf, IF idf, float ex,
-                                                float ey, const Params& p) {
+template <int kShift, class UF>
+__device__ __forceinline__ int best_hit_buckets(const uint16_t* lut, const Staged* plane, UF used, int64_t gbase,
+                                                float ex, float ey, const Params& p) {
     int lo[2], hi[2];
     const int nr = point_window(ex, ey, p.r_ext, lo, hi);
     float bq = 0.0f;
@@ -390,13 +390,14 @@ __device__ __forceinline__ int best_hit_buckets(const uint16_t* lut, KF key, UF 
         const int i0 = lut[lo[r] >> kShift], i1 = lut[(hi[r] >> kShift) + 1];
 #pragma unroll 4
         for (int i = i0; i < i1; ++i) {
-            const int k = key(i);
-            const float dx = xf(i) - ex;
-            const float dy = yf(i) - ey;
+            const Staged h = plane[i];
+            const int k = (int)h.key;
             if (k < lo[r] || k > hi[r] || used(i)) continue;
+            const float dx = h.x - ex;
+            const float dy = h.y - ey;
             const float q = dx * dx + dy * dy;
             if (!(q <= p.e_max)) continue;
-            const int id = idf(i);
+            const int id = (int)(h.id - gbase);
             if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
         }
     }
@@ -415,7 +416,7 @@ __device__ __forceinline__ int best_hit_grid(const Work& w, const int32_t* cs, i
         const float dy = w.g_gy[g + q0] - ey;
         const float q = dx * dx + dy * dy;
         if (!(q <= p.e_max)) return;
-        const int id = (int)(w.sid[g + i] - g);
+        const int id = (int)(w.stg[g + i].id - g);
         if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
     });
     return want;
@@ -464,11 +465,12 @@ __device__ __forceinline__ void prefetch_plane(const Scalars& sc, const FindArgs
     for (int r = 0; r < kPF; ++r) {
         const int i = threadIdx.x + r * kT;
         if (i < n) {
-            pf.x[r] = a.w.sx[g + i];
-            pf.y[r] = a.w.sy[g + i];
-            pf.key[r] = a.w.skey[g + i];
-            pf.kprev[r] = i ? (int)a.w.skey[g + i - 1] : -1;
-            pf.id[r] = (int)(a.w.sid[g + i] - g);
+            const Staged h = a.w.stg[g + i];
+            pf.x[r] = h.x;
+            pf.y[r] = h.y;
+            pf.key[r] = (int)h.key;
+            pf.kprev[r] = i ? (int)a.w.stg[g + i - 1].key : -1;
+            pf.id[r] = (int)(h.id - g);
         }
     }
 }
@@ -514,8 +516,10 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
         const int i = threadIdx.x + r * kT;
         if (i < n) put(i, pf.x[r], pf.y[r], pf.key[r], pf.kprev[r], pf.id[r]);
     }
-    for (int i = threadIdx.x + kPF * kT; i < n; i += kT)
-        put(i, a.w.sx[g + i], a.w.sy[g + i], a.w.skey[g + i], (int)a.w.skey[g + i - 1], (int)(a.w.sid[g + i] - g));
+    for (int i = threadIdx.x + kPF * kT; i < n; i += kT) {
+        const Staged h = a.w.stg[g + i];
+        put(i, h.x, h.y, (int)h.key, (int)a.w.stg[g + i - 1].key, (int)(h.id - g));
+    }
     if (n == 0)
         for (int b = threadIdx.x; b <= kN; b += kT) lut[b] = 0;
     if (n == 0)
@@ -563,13 +567,13 @@ __device__ void load_plane_global(S& st, int k) {
     } else {
         for (int i = threadIdx.x; i < n; i += kT) {
             lut_entries<kShift, kN>(lut, i, n, st.K(sl, i), i ? st.K(sl, i - 1) : -1);
-            atomicAdd(cs + grid_cell1(w.sy[g + i]) * kGridN + grid_cell1(w.sx[g + i]), 1);
+            atomicAdd(cs + grid_cell1(w.stg[g + i].y) * kGridN + grid_cell1(w.stg[g + i].x), 1);
         }
     }
     __syncthreads();
     block_excl_scan<kT>(cs, kCells, sc);
     for (int i = threadIdx.x; i < n; i += kT) {
-        const float x = w.sx[g + i], y = w.sy[g + i];
+        const float x = w.stg[g + i].x, y = w.stg[g + i].y;
         const int c = grid_cell1(y) * kGridN + grid_cell1(x);
         const int q = cs[c] + atomicAdd(fill + c, 1);
         w.g_gx[g + q] = x;
@@ -1066,10 +1070,10 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             const int64_t g = sc.cb[j];
             const Work& w = a.w;
             const int nj = (int)(sc.cb[j + 1] - g);
-            auto key = [&](int i) { return (int)w.skey[g + i]; };
-            auto xf = [&](int i) { return w.sx[g + i]; };
-            auto yf = [&](int i) { return w.sy[g + i]; };
-            auto idf = [&](int i) { return (int)(w.sid[g + i] - g); };
+            auto key = [&](int i) { return (int)w.stg[g + i].key; };
+            auto xf = [&](int i) { return w.stg[g + i].x; };
+            auto yf = [&](int i) { return w.stg[g + i].y; };
+            auto idf = [&](int i) { return (int)(w.stg[g + i].id - g); };
             if constexpr (S::kLarge) {
                 auto search = [&](float ex, float ey) { return best_hit_grid(w, st.cells(j), g, ex, ey, a.p); };
                 open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g), search,
@@ -1079,8 +1083,8 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
                 // its coarse bucket index, used flags in LDS
                 const uint16_t* clut = st.t->clut[j];
                 auto search = [&](float ex, float ey) {
-                    return best_hit_buckets<S::kCoarseShift>(clut, key, [&](int i) { return st.UP(j, i); }, xf, yf,
-                                                             idf, ex, ey, a.p);
+                    return best_hit_buckets<S::kCoarseShift>(clut, w.stg + g, [&](int i) { return st.UP(j, i); }, g,
+                                                             ex, ey, a.p);
                 };
                 open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(g), search,
                                               [&](int i) { st.set_UP(j, i); }, xf, yf, idf, g);

@@ -126,10 +126,7 @@ int64_t pool_entries(int32_t E, int64_t C) {
 size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, int64_t min_pool) {
     char* cur = base;
     const int64_t PX = std::max(P, C);
-    w.sx = carve<float>(cur, C);
-    w.sy = carve<float>(cur, C);
-    w.skey = carve<uint16_t>(cur, C);
-    w.sid = carve<int32_t>(cur, C);
+    w.stg = carve<Staged>(cur, C);
     w.used = carve<uint8_t>(cur, C);
     w.chits = carve<int32_t>(cur, C * kPlanes);
     w.cmask = carve<uint32_t>(cur, C);
