@@ -64,8 +64,9 @@ def main():
     g = [[buf[p * 12 + i] for i in range(12)] for p in range(3)]
     print(f"Workload {a.workload}: {b.n_events} events, {int(st[1]) / b.n_events:.0f} clusters/event; "
           f"launch {th} threads x tile {tl}; {a.reps} pipeline runs; phase-timing build.\n")
-    print("| pass | events | us/event (whole) | " + " | ".join(PHASES) + " | T3 steps/event ring, other |")
-    print("|---|---|---|" + "---|" * len(PHASES) + "---|")
+    print("| pass | events | us/event (whole) | " + " | ".join(PHASES) +
+          " | T3 steps/event on ring, other planes | us/event in T3 steps on other planes |")
+    print("|---|---|---|" + "---|" * len(PHASES) + "---|---|")
     for p in range(3):
         ev = g[p][8]
         if not ev:
@@ -75,7 +76,7 @@ def main():
         tot = sum(per)
         cells = " | ".join(f"{x:.1f} ({100 * x / tot:.0f} %)" for x in per)
         print(f"| {PASSES[p]} | {ev // a.reps} | {whole:.1f} | {cells} | "
-              f"{g[p][5] / ev:.1f}, {g[p][6] / ev:.1f} |")
+              f"{g[p][5] / ev:.1f}, {g[p][6] / ev:.1f} | {g[p][7] * TICK_US / ev:.1f} |")
 
 
 if __name__ == "__main__":
