@@ -1469,12 +1469,13 @@ template <int kT, bool kSeed>
 __global__ __launch_bounds__(kT) void k_find_large(FindArgs a, const float* __restrict__ seed_net) {
     __shared__ Scalars sc;
     __shared__ uint16_t luts[kRing][kLutLarge + 1];
-    __shared__ uint32_t hist[kRangeBins];
     __shared__ __align__(16) float seedw[kSeed ? kSeedFloats : 1];
-    __shared__ float seedh[kSeed ? kSeedH * kT : 1];
+    // the seed filter's activations; the key-range seeding's histogram shares
+    // the words (it is used only while no filter runs)
+    __shared__ __align__(16) float seedh[kSeed ? (kSeedH * kT > kRangeBins ? kSeedH * kT : kRangeBins) : kRangeBins];
     GlobalStore st{&sc, &a.w, 0, (int64_t)blockIdx.x * a.w.pool_cap, 0};
     st.luts = luts;
-    st.hist = hist;
+    st.hist = reinterpret_cast<uint32_t*>(seedh);
     st.seedh = seedh;
     if constexpr (kSeed) {
         // the seed network with its weight matrices back in [unit][input] rows
