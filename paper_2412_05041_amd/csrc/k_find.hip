@@ -451,7 +451,9 @@ __device__ void block_excl_scan(V* v, int n, Scalars& sc) {
 }
 
 // Registers holding the first hits of the next plane, loaded one step ahead so
-// that the global-memory latency overlaps the current step.
+// that the global-memory latency overlaps the current step.  The values stay
+// as loaded (the cluster index global) until the plane is written to the
+// ring: any arithmetic on them here would wait for the load right away.
 struct Prefetch {
     float x[2], y[2];
     int key[2], kprev[2], id[2];
@@ -470,7 +472,7 @@ __device__ __forceinline__ void prefetch_plane(const Scalars& sc, const FindArgs
             pf.y[r] = h.y;
             pf.key[r] = (int)h.key;
             pf.kprev[r] = i ? (int)a.w.stg[g + i - 1].key : -1;
-            pf.id[r] = (int)(h.id - g);
+            pf.id[r] = h.id;
         }
     }
 }
@@ -514,7 +516,7 @@ __device__ void load_plane_lds(S& st, const FindArgs& a, int k, const Prefetch& 
 #pragma unroll
     for (int r = 0; r < kPF; ++r) {
         const int i = threadIdx.x + r * kT;
-        if (i < n) put(i, pf.x[r], pf.y[r], pf.key[r], pf.kprev[r], pf.id[r]);
+        if (i < n) put(i, pf.x[r], pf.y[r], pf.key[r], pf.kprev[r], pf.id[r] - (int)g);
     }
     for (int i = threadIdx.x + kPF * kT; i < n; i += kT) {
         const Staged h = a.w.stg[g + i];
