@@ -54,10 +54,14 @@ constexpr float kKeysPerRad = 10430.378350470453f;  // 2^16 / (2 pi)
 // barrier: 0 plane load, 1 forwarding, 2 seed enumeration, 3 seed filter +
 // claiming, 4 track creation + downstream completion; then 5/6 downstream
 // completion steps on ring / non-ring planes, 7 ticks of the latter, 8
-// events, 9 ticks of whole events.
+// events, 9 ticks of whole events, 10 the part of the plane load that writes
+// the ring (LDS-tile passes; slot 0 then holds the next plane's prefetch).
 #ifdef VELO_PHASE_TIMING
-constexpr int kPhaseSlots = 12;
-__device__ unsigned long long g_phase[3][kPhaseSlots];
+// 64 copies of the counters, one per workgroup index modulo 64, so that the
+// counters' own atomics do not contend (they would hold up every later wait
+// on memory of the workgroups adding them); the probe sums the copies.
+constexpr int kPhaseSlots = 12, kPhaseCopies = 64;
+__device__ unsigned long long g_phase[3][kPhaseCopies][kPhaseSlots];
 __device__ __forceinline__ int phase_pass(const FindArgs& a) {
     return a.q_in == a.w.order ? 0 : (a.q_in == a.w.large ? 1 : 2);
 }
@@ -67,13 +71,13 @@ __device__ __forceinline__ int phase_pass(const FindArgs& a) {
         __syncthreads();                                                \
         if (threadIdx.x == 0) {                                         \
             const uint64_t now = wall_clock64();                        \
-            atomicAdd(&g_phase[phase_pass(a)][i], (unsigned long long)(now - ph_t)); \
+            atomicAdd(&g_phase[phase_pass(a)][blockIdx.x % kPhaseCopies][i], (unsigned long long)(now - ph_t)); \
             ph_t = now;                                                 \
         }                                                               \
     } while (0)
 #define PCOUNT(i, v)                                                    \
     do {                                                                \
-        if (threadIdx.x == 0) atomicAdd(&g_phase[phase_pass(a)][i], (unsigned long long)(v)); \
+        if (threadIdx.x == 0) atomicAdd(&g_phase[phase_pass(a)][blockIdx.x % kPhaseCopies][i], (unsigned long long)(v)); \
     } while (0)
 #define PCLOCK() wall_clock64()
 #define PHASE_END()                                                     \
@@ -1379,6 +1383,7 @@ __device__ bool find_event(S& st, const FindArgs& a, int e, const float* __restr
             load_plane_global<kT>(st, k);
         } else {
             load_plane_lds<kT, kPF>(st, a, k, pf);
+            PHASE(10);
             if (k > 0) prefetch_plane<kT, kPF>(sc, a, k - 1, pf);
         }
         PHASE(0);
@@ -1697,11 +1702,19 @@ hipError_t launch_finder_large(FindArgs a, hipStream_t s) {
 }
 
 #ifdef VELO_PHASE_TIMING
-// out: 3 passes x 12 slots (see g_phase); reset clears them afterwards.
+// out: 3 passes x 12 slots (see g_phase), summed over the copies; reset
+// clears them afterwards.
 extern "C" int velo_probe_phase(unsigned long long* out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return -1;
+    static unsigned long long buf[3][kPhaseCopies][kPhaseSlots];
+    if (hipMemcpyFromSymbol(buf, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return -1;
+    for (int p = 0; p < 3; ++p)
+        for (int i = 0; i < kPhaseSlots; ++i) {
+            unsigned long long t = 0;
+            for (int c = 0; c < kPhaseCopies; ++c) t += buf[p][c][i];
+            out[p * kPhaseSlots + i] = t;
+        }
     if (reset) {
-        unsigned long long z[3 * kPhaseSlots] = {};
+        static const unsigned long long z[3][kPhaseCopies][kPhaseSlots] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return -1;
     }
     return 0;

@@ -64,18 +64,20 @@ def main():
     g = [[buf[p * 12 + i] for i in range(12)] for p in range(3)]
     print(f"Workload {a.workload}: {b.n_events} events, {int(st[1]) / b.n_events:.0f} clusters/event; "
           f"launch {th} threads x tile {tl}; {a.reps} pipeline runs; phase-timing build.\n")
-    print("| pass | events | us/event (whole) | " + " | ".join(PHASES) +
+    print("| pass | events | us/event (whole) | plane load: ring write | " + " | ".join(PHASES) +
           " | T3 steps/event on ring, other planes | us/event in T3 steps on other planes |")
-    print("|---|---|---|" + "---|" * len(PHASES) + "---|---|")
+    print("|---|---|---|---|" + "---|" * len(PHASES) + "---|---|")
     for p in range(3):
         ev = g[p][8]
         if not ev:
             continue
         per = [g[p][i] * TICK_US / ev for i in range(5)]
+        ring = g[p][10] * TICK_US / ev
+        per[0] += ring  # the plane load: ring write, then issuing the prefetch
         whole = g[p][9] * TICK_US / ev
         tot = sum(per)
         cells = " | ".join(f"{x:.1f} ({100 * x / tot:.0f} %)" for x in per)
-        print(f"| {PASSES[p]} | {ev // a.reps} | {whole:.1f} | {cells} | "
+        print(f"| {PASSES[p]} | {ev // a.reps} | {whole:.1f} | {ring:.1f} | {cells} | "
               f"{g[p][5] / ev:.1f}, {g[p][6] / ev:.1f} | {g[p][7] * TICK_US / ev:.1f} |")
 
 
