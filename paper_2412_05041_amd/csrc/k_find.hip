@@ -260,30 +260,49 @@ struct GlobalStore {
 
 // ---------------------------------------------------------------- windows
 
-// Up to two inclusive key ranges covering azimuths [phi - half, phi + half].
-__device__ __forceinline__ int key_ranges(float phi, float half, int* lo, int* hi) {
-    if (!(half < 3.0f)) { lo[0] = 0; hi[0] = 65535; return 1; }
-    const float a = phi - half, b = phi + half;
-    if (a < -kPi) {
-        lo[0] = phi_key(a + kTwoPi); hi[0] = 65535;
-        lo[1] = 0; hi[1] = phi_key(b);
+// Key ranges covering keys [a - m, b + m] on the key circle (a <= b, as plain
+// integers possibly outside [0, 65535]).
+__device__ __forceinline__ int key_span(int a, int b, int m, int* lo, int* hi) {
+    int l = a - m, h = b + m;
+    if (h - l >= 65535) { lo[0] = 0; hi[0] = 65535; return 1; }
+    if (l < 0) {
+        lo[0] = l + 65536; hi[0] = 65535;
+        lo[1] = 0; hi[1] = h;
         return 2;
     }
-    if (b > kPi) {
-        lo[0] = phi_key(a); hi[0] = 65535;
-        lo[1] = 0; hi[1] = phi_key(b - kTwoPi);
+    if (h > 65535) {
+        lo[0] = l; hi[0] = 65535;
+        lo[1] = 0; hi[1] = h - 65536;
         return 2;
     }
-    lo[0] = phi_key(a); hi[0] = phi_key(b);
+    lo[0] = l; hi[0] = h;
     return 1;
 }
 
-// Window of hits within distance R of the point (ex, ey): half-angle asin(R/r).
+// Key ranges covering every key position within asin(R/|E|) of the azimuth of
+// E = (ex, ey), from cheap bounds rather than atan2f and asinf:
+//   * the azimuth of E: an octant reduction to atan(t), |t| <= 1, evaluated
+//     with the odd degree-9 polynomial of Abramowitz & Stegun 4.4.49 (Hastings;
+//     |error| about 1e-5 rad) and the hardware reciprocal;
+//   * the half-angle: asin(x) <= tan(asin(x)) = R / sqrt(|E|^2 - R^2), from the
+//     hardware reciprocal square root, widened by 0.1 %;
+// then 1e-4 rad and two keys on each side absorb the polynomial's error, FP32
+// rounding, the truncation of the staged keys and their clamp at 65535.  A
+// point within 2R of the axis takes the whole circle.
 __device__ __forceinline__ int point_window(float ex, float ey, float R, int* lo, int* hi) {
-    const float r = sqrtf(ex * ex + ey * ey);
-    if (!(r > R * 1.001f + 1e-3f)) { lo[0] = 0; hi[0] = 65535; return 1; }
-    const float half = asinf(R / r) * 1.0001f + 2e-4f;
-    return key_ranges(atan2f(ey, ex), half, lo, hi);
+    const float e2 = ex * ex + ey * ey;
+    if (!(e2 > 4.0f * R * R)) { lo[0] = 0; hi[0] = 65535; return 1; }
+    const float half = R * __builtin_amdgcn_rsqf(e2 - R * R) * 1.001f + 1e-4f;
+    const float ax = fabsf(ex), ay = fabsf(ey);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float s = t * t;
+    float phi = t * (0.9998660f + s * (-0.3302995f + s * (0.1801410f + s * (-0.0851330f + s * 0.0208351f))));
+    if (ay > ax) phi = 1.57079633f - phi;
+    if (ex < 0.0f) phi = kPi - phi;
+    if (ey < 0.0f) phi = -phi;
+    const float c = (phi + kPi) * kKeysPerRad;
+    const float w = half * kKeysPerRad;
+    return key_span((int)floorf(c - w) - 2, (int)ceilf(c + w) + 2, 0, lo, hi);
 }
 
 // Grid cell (one axis) of a coordinate; monotone in v, clamped to the grid.
@@ -331,25 +350,6 @@ __device__ __forceinline__ void visit(LF lower, KF key, int n, int nr, const int
     for (int r = 0; r < nr; ++r) {
         for (int i = lower(lo[r]); i < n && key(i) <= hi[r]; ++i) f(i);
     }
-}
-
-// Key ranges covering keys [a - m, b + m] on the key circle (a <= b, as plain
-// integers possibly outside [0, 65535]).
-__device__ __forceinline__ int key_span(int a, int b, int m, int* lo, int* hi) {
-    int l = a - m, h = b + m;
-    if (h - l >= 65535) { lo[0] = 0; hi[0] = 65535; return 1; }
-    if (l < 0) {
-        lo[0] = l + 65536; hi[0] = 65535;
-        lo[1] = 0; hi[1] = h;
-        return 2;
-    }
-    if (h > 65535) {
-        lo[0] = l; hi[0] = 65535;
-        lo[1] = 0; hi[1] = h - 65536;
-        return 2;
-    }
-    lo[0] = l; hi[0] = h;
-    return 1;
 }
 
 // Half-width in keys of the azimuth range subtended by a disc of radius R seen
@@ -685,20 +685,17 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
     auto lower1 = [&](int v) { return lower_lut<S::kLutShift>(lut1, key1, n1, v); };
     auto lower2 = [&](int v) { return lower_lut<S::kLutShift>(lut2, key2, n2, v); };
     int32_t* pref = st.pref();        // [n0 + 1]
-    int32_t* eb = st.ebuf();          // a0[n0], b0[n0], a1[n0], b1[n0], m1[n0]
+    int32_t* eb = st.ebuf();          // a0[n0], b0[n0], a1[n0], b1[n0]
     // (A) windows.  An outward line through h0 passing within D of the axis
-    // keeps every later point within asin(D/r0) of h0's azimuth, and its
-    // radius grows: h2 lies in that wedge, and the predicted middle point lies
-    // between the azimuths of h0 and h2 at radius >= r0, so h1 is within
-    // asin(R_mid/r0) of that arc.
+    // keeps every later point within asin(D/r0) of h0's azimuth: h2 lies in
+    // that wedge.
     auto window = [&](int i0) {
-        int cnt = 0, ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0, m1 = 0;
+        int cnt = 0, ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0;
         if (!st.U(s0, k, i0)) {
             const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
             const int k0 = st.K(s0, i0);
             const float r0 = sqrtf(x0 * x0 + y0 * y0);
             const int mD = disc_keys(p.r_seed, r0);
-            m1 = disc_keys(p.r_mid, r0);
             int lo[2], hi[2];
             const int nr = mD < 0 ? (lo[0] = 0, hi[0] = 65535, 1) : key_span(k0, k0, mD, lo, hi);
             ra0 = lower2(lo[0]);
@@ -713,7 +710,6 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
         eb[n0 + i0] = rb0;
         eb[2 * n0 + i0] = ra1;
         eb[3 * n0 + i0] = rb1;
-        eb[4 * n0 + i0] = m1;
         return cnt;
     };
     if (n0 <= kT) {
@@ -800,13 +796,9 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
             grid_visit(st.cells(k + 1), ex, ey, p.r_mid,
                        [&](int q1) { try_mid(a.w.g_gpos[g1 + q1], a.w.g_gx[g1 + q1], a.w.g_gy[g1 + q1]); });
         } else {
-            const int k0 = st.K(s0, i0);
-            const int m1 = eb[4 * n0 + i0];
-            int kd = st.K(s2, i2) - k0;  // signed azimuth difference in keys, shorter arc
-            kd = kd > 32767 ? kd - 65536 : (kd < -32768 ? kd + 65536 : kd);
+            // the disc of radius R_mid around the predicted middle point
             int lo1[2], hi1[2];
-            const int nr1 = m1 < 0 ? (lo1[0] = 0, hi1[0] = 65535, 1)
-                                   : key_span(k0 + min(kd, 0), k0 + max(kd, 0), m1, lo1, hi1);
+            const int nr1 = point_window(ex, ey, p.r_mid, lo1, hi1);
             visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) { try_mid(i1, st.X(s1, i1), st.Y(s1, i1)); });
         }
     }
