@@ -148,6 +148,16 @@ int velo_reserve(velo_ctx* ctx, int32_t max_events, int64_t max_pixels, int64_t 
  * the pool to all of the reservation. */
 int velo_set_large_pool(velo_ctx* ctx, int64_t entries);
 
+/* Routing of events between the finder's passes (performance only: every pass
+ * gives the same tracks).  An event whose clusters exceed clusters_per_track x
+ * the track capacity of an LDS tile skips that tile and goes straight to the
+ * next pass, as an event with a plane larger than the tile does; without the
+ * rule such an event would most likely run out of track slots late in its plane
+ * walk and be redone.  Collision events create about one candidate track per
+ * 15 clusters; the default, 13.5, routes those that would overflow the first
+ * tile.  0 turns the rule off (planes alone decide). */
+int velo_set_admission(velo_ctx* ctx, float clusters_per_track);
+
 /* Pixel clustering (connected components, 8-neighbourhood).
  *   in : d_pix_off[n_events*26+1] int32, d_pix_id[...] uint32
  *   out: d_pix_clu[n_pix] global cluster index of each pixel,

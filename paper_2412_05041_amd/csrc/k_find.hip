@@ -1446,10 +1446,13 @@ __global__ __launch_bounds__(kT, (find_waves_per_eu<kT, kP>())) void k_find_lds(
             __syncthreads();
             continue;
         }
-        // admission: every plane must fit the tile
+        // admission: every plane must fit the tile, and the event must not be
+        // so large that it would likely run out of track slots
         int big = 0;
         for (int k = threadIdx.x; k < kPlanes; k += kT)
             big |= (a.clu_off[e * kPlanes + k + 1] - a.clu_off[e * kPlanes + k]) > kP;
+        if (threadIdx.x == 0 && a.admit > 0.0f)
+            big |= (float)(a.clu_off[(e + 1) * kPlanes] - a.clu_off[e * kPlanes]) > a.admit * (float)kTr;
         big = __syncthreads_or(big);
         bool ok = false;
         if (!big) {

@@ -40,6 +40,9 @@ struct FindArgs {
     const float* mlp_master;  // learned mode: FP32 master weights (device)
     const float* mlp_norm;    // 20 floats
     int64_t clu_limit;        // events whose clusters reach beyond this are not processed
+    // LDS-tile admission: an event with more clusters than admit x (the tile's
+    // track capacity) goes straight to the next pass (0: planes alone decide)
+    float admit;
     // event queue of an LDS-tile pass: events q_in[0 .. n) with n = n_events
     // (q_count < 0) or counters[q_count], taken through counters[q_cursor];
     // events that do not fit go to q_out, counted in counters[q_out_count]

@@ -18,6 +18,11 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Clusters per track slot above which an event skips an LDS tile: collision
+// events create about one candidate track per 15 clusters (noise included), and
+// nearly every one above 13.5 per slot runs out of the first tile's slots.
+constexpr float kDefaultAdmit = 13.5f;
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -48,6 +53,7 @@ struct velo_ctx {
     int validate = 0;
     int threads = 256, tile = 1;
     int64_t pool_limit = 0;  // velo_set_large_pool (0: the reserved pool)
+    float admit = kDefaultAdmit;  // velo_set_admission
     Work w{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -243,6 +249,7 @@ int enqueue_find_out(velo_ctx* c, int32_t E, const int32_t* clu_off, const float
     fa.mlp_master = c->mlp.d_master;
     fa.mlp_norm = c->mlp.d_norm;
     fa.clu_limit = clu_limit;
+    fa.admit = c->admit;
     fa.seed_net = c->seed_on ? c->d_seed : nullptr;
     fa.seed_feat = c->seed_feat;
     fa.seed_hits = c->seed_hits;
@@ -338,6 +345,7 @@ int enqueue_tune_batch(velo_ctx* c, int32_t E, const int32_t* clu_off, const flo
     fa.p.mode = 0;
     fa.w = c->w;
     fa.clu_limit = c->w.cap_clusters;
+    fa.admit = c->admit;
     fa.seed_net = c->seed_on ? c->d_seed : nullptr;
     if (int rc = enqueue_finder(c, fa, E, s, false)) return rc;
     HIP_OK(launch_accept(fa, s));
@@ -542,6 +550,15 @@ int velo_reserve(velo_ctx* c, int32_t max_events, int64_t max_pixels, int64_t ma
     c->ws = base;
     c->ws_bytes = bytes;
     c->pool_limit = 0;
+    c->version++;
+    return VELO_OK;
+}
+
+int velo_set_admission(velo_ctx* c, float clusters_per_track) {
+    if (!c) return fail(VELO_ERR_ARG, "null context");
+    if (!(clusters_per_track >= 0.0f) || !std::isfinite(clusters_per_track))
+        return fail(VELO_ERR_ARG, "clusters per track must be finite and >= 0");
+    c->admit = clusters_per_track;
     c->version++;
     return VELO_OK;
 }

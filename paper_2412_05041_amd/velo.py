@@ -54,6 +54,7 @@ _SIGS = {
                      [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p],
     "velo_set_launch": [C.c_void_p, C.c_int32, C.c_int32],
     "velo_set_large_pool": [C.c_void_p, C.c_int64],
+    "velo_set_admission": [C.c_void_p, C.c_float],
     "velo_get_launch": [C.c_void_p, C.c_void_p, C.c_void_p],
     "velo_autotune": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                       C.c_char_p, C.c_void_p, C.c_void_p],
@@ -165,6 +166,9 @@ class Velo:
 
     def set_large_pool(self, entries: int):
         _check(lib().velo_set_large_pool(self.h, int(entries)))
+
+    def set_admission(self, clusters_per_track: float):
+        _check(lib().velo_set_admission(self.h, float(clusters_per_track)))
 
     def set_launch(self, threads: int, tile: int):
         _check(lib().velo_set_launch(self.h, threads, tile))
