@@ -24,21 +24,36 @@ struct FitResult {
 };
 
 // Gathers the coordinates of a track's hits into per-plane registers:
-// hit_at(k, i) gives the cluster index of the i-th hit (on plane k).  Fully
-// unrolled over the 26 planes, so the loads are independent and issue together.
+// hit_at(k, i) gives the cluster index of the i-th hit (on plane k).  Two
+// rounds of independent loads with no branch between a load and its use, so
+// that each round waits once: every plane's hit index (hit_at is called for
+// every plane, with i clamped to the last hit, and must be safe to read
+// there), then every plane's coordinates, planes off the mask reading the
+// first hit's.  Planes off the mask get 0.
 template <typename HitAt>
 __device__ __forceinline__ void gather_hits(HitAt hit_at, uint32_t mask, const float* clu_x, const float* clu_y,
                                             float* x, float* y) {
+    const int n = __popc(mask);
+    if (n == 0) {
+#pragma unroll
+        for (int k = 0; k < kPlanes; ++k) { x[k] = 0.0f; y[k] = 0.0f; }
+        return;
+    }
+    const int first = __ffs(mask) - 1;
+    int h[kPlanes];
+#pragma unroll
+    for (int k = 0; k < kPlanes; ++k) h[k] = hit_at(k, min(__popc(mask & ((1u << k) - 1u)), n - 1));
+    int h0 = h[0];
+#pragma unroll
+    for (int k = 1; k < kPlanes; ++k) h0 = k == first ? h[k] : h0;
 #pragma unroll
     for (int k = 0; k < kPlanes; ++k) {
-        if (mask & (1u << k)) {
-            const int h = hit_at(k, __popc(mask & ((1u << k) - 1u)));
-            x[k] = clu_x[h];
-            y[k] = clu_y[h];
-        } else {
-            x[k] = 0.0f;
-            y[k] = 0.0f;
-        }
+        const bool on = (mask >> k) & 1u;
+        const int hk = on ? h[k] : h0;
+        const float xv = clu_x[hk];
+        const float yv = clu_y[hk];
+        x[k] = on ? xv : 0.0f;
+        y[k] = on ? yv : 0.0f;
     }
 }
 

@@ -19,7 +19,9 @@ namespace velo {
 
 namespace {
 
-constexpr int kCap = 512;            // pixels of a segment handled in LDS
+constexpr int kCap = 1024;           // pixels of a segment handled in LDS
+constexpr int kStageCap = 512;       // clusters of a segment staged from registers and LDS
+static_assert(kCap < (1 << 11) && (int64_t)kCap * (kSide - 1) < (1 << 21), "a segment's packed sums fit their fields");
 constexpr int kSmallBuckets = 256;   // staging buckets for segments in LDS
 
 template <typename P>
@@ -208,14 +210,23 @@ __device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsi
     int32_t* s_par = reinterpret_cast<int32_t*>(s_id + kCap);
     const int lane = threadIdx.x;
     const Work& w = a.w;
+    if (n == 0) {
+        if (lane == 0) w.seg_m[seg] = 0;
+        return;
+    }
+    // All R loads are issued before the first is used (addresses clamped into
+    // the segment), so the wave waits for the ids once, not once per row.
     uint32_t id[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) id[r] = a.pix_id[p0 + min(lane + r * kWave, n - 1)];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lane + r * kWave;
-        id[r] = i < n ? a.pix_id[p0 + i] : 0u;
         if (i < n) {
             s_id[i] = id[r];
             s_par[i] = i;
+        } else {
+            id[r] = 0u;
         }
     }
     __syncthreads();
@@ -265,7 +276,8 @@ __device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsi
     for (int r = 0; r < R; ++r) rank[r] = root[r] >= 0 ? s_par[root[r]] : 0;
     __syncthreads();
     // ids and parents are dead: the same words hold the packed sums
-    // [sum_c:32 | count:11 | sum_r:21]; n <= 512 keeps the fields apart
+    // [sum_c:32 | count:11 | sum_r:21]; n <= kCap = 1024 keeps the fields apart
+    // (count <= 1024 < 2^11, sum_r <= 1024 * 1453 < 2^21)
     unsigned long long* s_sum = s_buf;
     for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
     __syncthreads();
@@ -366,16 +378,135 @@ __global__ __launch_bounds__(1024) void k_scan_seg(ClusterArgs a) {
 }
 
 // Global numbering, centroid output and (fused pipeline) staging.
-// LDS of a staging wave, 4 KB: a segment of at most kCap clusters sorts in it
+// LDS of a staging wave, 4 KB: a segment of at most kStageCap clusters sorts in it
 // (keys, 16-bit positions, kSmallBuckets counters); a larger one keeps its
 // keys and positions in the per-pixel scratch and its kBuckets counters here.
 struct StageLds {
     uint32_t w[kBuckets];
     __device__ uint32_t* keys() { return w; }
-    __device__ uint16_t* pos() { return reinterpret_cast<uint16_t*>(w + kCap); }
-    __device__ uint32_t* hist_small() { return w + kCap + kCap / 2; }
-    static_assert(kCap + kCap / 2 + kSmallBuckets <= kBuckets, "the small layout fits");
+    __device__ uint16_t* pos() { return reinterpret_cast<uint16_t*>(w + kStageCap); }
+    __device__ uint32_t* hist_small() { return w + kStageCap + kStageCap / 2; }
+    static_assert(kStageCap + kStageCap / 2 + kSmallBuckets <= kBuckets, "the small layout fits");
 };
+
+// Azimuth-sorted staging by (key, index) of m <= kStageCap clusters whose
+// coordinates a wave holds in registers (cluster j = lane + 64 r): bucket
+// counts, bucket starts, bucket members, then each cluster's rank among its
+// bucket's members.  Staged entry cb + rank holds x, y, key and the global
+// cluster index cb + j.
+__device__ void stage_regs(const float (&cx)[kStageCap / kWave], const float (&cy)[kStageCap / kWave], int m,
+                           int64_t cb, StageLds& lds, const Work& w) {
+    constexpr int RM = kStageCap / kWave;
+    constexpr int kNb = kSmallBuckets;
+    constexpr int kShift = kKeyBits - __builtin_ctz(kNb);
+    const int lane = threadIdx.x;
+    uint32_t* kbuf = lds.keys();
+    uint16_t* tbuf = lds.pos();
+    uint32_t* hist = lds.hist_small();
+    for (int b = lane; b < kNb; b += kWave) hist[b] = 0;
+    __syncthreads();
+    uint32_t key[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int j = lane + r * kWave;
+        key[r] = 0;
+        if (j < m) {
+            key[r] = (uint32_t)phi_key(atan2f(cy[r], cx[r]));
+            kbuf[j] = key[r];
+            atomicAdd(hist + (key[r] >> kShift), 1u);
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int per = kNb / kWave;
+        uint32_t loc[per];
+        uint32_t t = 0;
+#pragma unroll
+        for (int i = 0; i < per; ++i) { loc[i] = hist[lane * per + i]; t += loc[i]; }
+        int tot;
+        uint32_t run = (uint32_t)wave_excl_scan((int)t, &tot);
+#pragma unroll
+        for (int i = 0; i < per; ++i) { hist[lane * per + i] = run; run += loc[i]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int j = lane + r * kWave;
+        if (j < m) tbuf[atomicAdd(hist + (key[r] >> kShift), 1u)] = (uint16_t)j;
+    }
+    __syncthreads();
+    // hist[b] is now the end of bucket b
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int j = lane + r * kWave;
+        if (j < m) {
+            const uint32_t kj = key[r];
+            const int b = (int)(kj >> kShift);
+            const int e = (int)hist[b];
+            int rank = b ? (int)hist[b - 1] : 0;
+            for (int q = rank; q < e; ++q) {
+                const int i = tbuf[q];
+                const uint32_t ki = kbuf[i];
+                rank += (ki < kj || (ki == kj && i < j)) ? 1 : 0;
+            }
+            const int64_t g = cb + rank;
+            w.stg[g] = Staged{cx[r], cy[r], (int32_t)(cb + j), kj};
+            w.used[g] = 0;
+        }
+    }
+}
+
+// Global numbering, centroid output and staging of a segment of at most kCap
+// pixels and kStageCap clusters, one wave.  Every global load (the segment's
+// local labels and parked centroids) is issued at once into registers, with
+// addresses clamped into the segment; the staging then works from registers
+// and LDS.  Same outputs as the general loops of k_cluster_final.
+__device__ void final_small(const ClusterArgs& a, int seg, int p0, int n, int64_t cb, int m, StageLds& lds) {
+    constexpr int R = kCap / kWave;
+    constexpr int RM = kStageCap / kWave;
+    const int lane = threadIdx.x;
+    const Work& w = a.w;
+    int32_t lab[R];
+    float cx[RM], cy[RM];
+    uint32_t cnt[RM];
+    if (n > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lab[r] = a.pix_clu[p0 + min(lane + r * kWave, n - 1)];
+    }
+    if (m > 0) {
+        const float* tx = reinterpret_cast<const float*>(w.g_sc + p0);
+        const float* ty = reinterpret_cast<const float*>(w.g_sr + p0);
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            const int j = min(lane + r * kWave, m - 1);
+            cx[r] = tx[j];
+            cy[r] = ty[j];
+            cnt[r] = w.g_cnt[p0 + j];
+        }
+    }
+    if (n > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + r * kWave;
+            if (i < n && lab[r] >= 0) a.pix_clu[p0 + i] = (int32_t)(cb + lab[r]);
+        }
+    }
+    if (m <= 0) return;
+    if (cb + m > a.clu_cap) {
+        if (lane == 0) set_event_flag(a.status, seg / kPlanes, EV_OVERFLOW, 1);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int j = lane + r * kWave;
+        if (j < m) {
+            a.clu_x[cb + j] = cx[r];
+            a.clu_y[cb + j] = cy[r];
+            if (a.clu_npix) a.clu_npix[cb + j] = (int32_t)cnt[r];
+        }
+    }
+    if (a.stage) stage_regs(cx, cy, m, cb, lds, w);
+}
 
 __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
     __shared__ StageLds s_lds;
@@ -386,7 +517,13 @@ __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
     const int n = a.pix_off[seg + 1] - p0;
     const int64_t cb = a.clu_off[seg];
     const int m = a.clu_off[seg + 1] - (int)cb;
-    if ((int64_t)p0 + n > w.cap_scratch) return;  // refused in the first pass
+    // refused in the first pass (m is always >= 0: the test only makes the
+    // branch need both offset loads, so that they are in flight together)
+    if (((int64_t)p0 + n > w.cap_scratch) | (m < 0)) return;
+    if (n <= kCap && m <= kStageCap) {
+        final_small(a, seg, p0, n, cb, m, s_lds);
+        return;
+    }
     for (int i = threadIdx.x; i < n; i += kWave) {
         const int32_t v = a.pix_clu[p0 + i];
         if (v >= 0) a.pix_clu[p0 + i] = (int32_t)(cb + v);
@@ -404,7 +541,7 @@ __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
         if (a.clu_npix) a.clu_npix[cb + j] = (int32_t)w.g_cnt[p0 + j];
     }
     if (!a.stage) return;
-    if (m <= kCap) {
+    if (m <= kStageCap) {
         stage_segment<kSmallBuckets>(tx, ty, m, cb, s_lds.keys(), s_lds.pos(), s_lds.hist_small(), w);
     } else {
         stage_segment<kBuckets>(tx, ty, m, cb, (uint32_t*)(w.g_par + p0), w.g_tmp + p0, s_lds.w, w);
@@ -419,9 +556,17 @@ __global__ __launch_bounds__(kWave) void k_stage(StageArgs a) {
     const int64_t cb = a.clu_off[seg];
     const int m = a.clu_off[seg + 1] - (int)cb;
     if (m <= 0 || cb + m > a.w.cap_clusters) return;  // the finder flags such events
-    if (m <= kCap) {
-        stage_segment<kSmallBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, s_lds.keys(), s_lds.pos(),
-                                     s_lds.hist_small(), a.w);
+    if (m <= kStageCap) {
+        // coordinates loaded at once into registers (addresses clamped into the segment)
+        constexpr int RM = kStageCap / kWave;
+        float cx[RM], cy[RM];
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            const int64_t j = cb + min((int)threadIdx.x + r * kWave, m - 1);
+            cx[r] = a.clu_x[j];
+            cy[r] = a.clu_y[j];
+        }
+        stage_regs(cx, cy, m, cb, s_lds, a.w);
     } else {
         stage_segment<kBuckets>(a.clu_x + cb, a.clu_y + cb, m, cb, (uint32_t*)(a.w.g_par + cb), a.w.g_tmp + cb,
                                 s_lds.w, a.w);

@@ -381,28 +381,38 @@ __device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf,
 
 // best_hit on a plane read from global memory through a bucket index: every
 // position of the buckets the key ranges touch is visited -- the bounds come
-// from the index alone, so the loads of one search do not wait for each other
-// -- and the key test inside keeps exactly the positions best_hit visits.
+// from the index alone -- and the key test inside keeps exactly the positions
+// best_hit visits.  The positions are read four at a time into separate
+// registers (the last group's spare reads repeat its last position and are
+// skipped), so that a search waits once per group, not once per hit; the
+// skip test uses non-short-circuit operators so that each read is used
+// unconditionally and stays where it is issued.
 template <int kShift, class UF>
 __device__ __forceinline__ int best_hit_buckets(const uint16_t* lut, const Staged* plane, UF used, int64_t gbase,
                                                 float ex, float ey, const Params& p) {
+    constexpr int kB = 4;
     int lo[2], hi[2];
     const int nr = point_window(ex, ey, p.r_ext, lo, hi);
     float bq = 0.0f;
     int bid = kIntMax, want = -1;
     for (int r = 0; r < nr; ++r) {
         const int i0 = lut[lo[r] >> kShift], i1 = lut[(hi[r] >> kShift) + 1];
-#pragma unroll 4
-        for (int i = i0; i < i1; ++i) {
-            const Staged h = plane[i];
-            const int k = (int)h.key;
-            if (k < lo[r] || k > hi[r] || used(i)) continue;
-            const float dx = h.x - ex;
-            const float dy = h.y - ey;
-            const float q = dx * dx + dy * dy;
-            if (!(q <= p.e_max)) continue;
-            const int id = (int)(h.id - gbase);
-            if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+        for (int b = i0; b < i1; b += kB) {
+            Staged h[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) h[u] = plane[min(b + u, i1 - 1)];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int i = b + u;
+                const int k = (int)h[u].key;
+                if (((i >= i1) | (k < lo[r]) | (k > hi[r])) || used(i)) continue;
+                const float dx = h[u].x - ex;
+                const float dy = h[u].y - ey;
+                const float q = dx * dx + dy * dy;
+                if (!(q <= p.e_max)) continue;
+                const int id = (int)(h[u].id - gbase);
+                if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+            }
         }
     }
     return want;

@@ -153,15 +153,26 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
                 a.trk_planes[t] = mask;
                 if (a.trk_flags) a.trk_flags[t] = fl;
                 if (a.trk_logit) a.trk_logit[t] = w.clogit[slot0 + c];
+                // every plane slot of the candidate (and its fit) is read
+                // before the first store, so that the copy waits once
                 const int32_t* ch = w.chits + (slot0 + c) * kPlanes;
-                int j = 0;
-                for (int k = 0; k < kPlanes; ++k)
-                    if (mask & (1u << k)) a.trk_hit[h + j++] = ch[k];
+                int32_t hv[kPlanes];
+#pragma unroll
+                for (int k = 0; k < kPlanes; ++k) hv[k] = ch[k];
+                float4 f0, f1;
                 if (a.par) {  // the acceptance step's fit of these hits (same function, same bits)
                     const float4* src = reinterpret_cast<const float4*>(w.cpar + (slot0 + c) * 8);
+                    f0 = src[0];
+                    f1 = src[1];
+                }
+                int j = 0;
+#pragma unroll
+                for (int k = 0; k < kPlanes; ++k)
+                    if (mask & (1u << k)) a.trk_hit[h + j++] = hv[k];
+                if (a.par) {
                     float4* dst = reinterpret_cast<float4*>(a.par + t * 8);
-                    dst[0] = src[0];
-                    dst[1] = src[1];
+                    dst[0] = f0;
+                    dst[1] = f1;
                 }
             } else {
                 overflow = true;
