@@ -343,12 +343,19 @@ __device__ __forceinline__ int lower_lut(const uint16_t* lut, KF key, int n, int
     return i;
 }
 
-// Visits every position of a key-sorted plane whose key lies in the ranges;
-// lower(v) is the first position with key >= v.
-template <class LF, class KF, class F>
-__device__ __forceinline__ void visit(LF lower, KF key, int n, int nr, const int* lo, const int* hi, F f) {
+// Visits every position of a key-sorted plane whose key lies in the ranges
+// lo[r] .. hi[r], through its bucket index lut (lut[b] = first position whose
+// key bucket is >= b): every position of the buckets a range touches, with
+// the key test inside.  The ends of a range are not searched for, so a visit
+// starts after one index read instead of a chain of key reads.
+template <int kShift, class KF, class F>
+__device__ __forceinline__ void visit_lut(const uint16_t* lut, KF key, int nr, const int* lo, const int* hi, F f) {
     for (int r = 0; r < nr; ++r) {
-        for (int i = lower(lo[r]); i < n && key(i) <= hi[r]; ++i) f(i);
+        const int i1 = lut[(hi[r] >> kShift) + 1];
+        for (int i = lut[lo[r] >> kShift]; i < i1; ++i) {
+            const int k = key(i);
+            if (k >= lo[r] && k <= hi[r]) f(i);
+        }
     }
 }
 
@@ -359,15 +366,16 @@ __device__ __forceinline__ int disc_keys(float R, float r) {
     return (int)ceilf((asinf(R / r) * 1.0001f + 2e-4f) * kKeysPerRad) + 2;
 }
 
-// Best unused hit (q, index) within e_max of (ex, ey) on a staged plane.
-template <class LF, class KF, class UF, class XF, class YF, class IF>
-__device__ __forceinline__ int best_hit(LF lower, KF key, UF used, XF xf, YF yf, IF idf, int n, float ex, float ey,
+// Best unused hit (q, index) within e_max of (ex, ey) on a staged plane in
+// LDS with bucket index lut.
+template <int kShift, class KF, class UF, class XF, class YF, class IF>
+__device__ __forceinline__ int best_hit(const uint16_t* lut, KF key, UF used, XF xf, YF yf, IF idf, float ex, float ey,
                                         const Params& p) {
     int lo[2], hi[2];
     const int nr = point_window(ex, ey, p.r_ext, lo, hi);
     float bq = 0.0f;
     int bid = kIntMax, want = -1;
-    visit(lower, key, n, nr, lo, hi, [&](int i) {
+    visit_lut<kShift>(lut, key, nr, lo, hi, [&](int i) {
         if (used(i)) return;
         const float dx = xf(i) - ex;
         const float dy = yf(i) - ey;
@@ -620,10 +628,9 @@ __device__ void forward(S& st, const FindArgs& a, int k) {
             } else {
                 const uint16_t* lut = st.lut(sl);
                 auto key = [&](int i) { return st.K(sl, i); };
-                want = best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, n, v); }, key,
-                                [&](int i) { return st.U(sl, k, i); },
-                                [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
-                                [&](int i) { return st.L(sl, i); }, n, ex, ey, p);
+                want = best_hit<S::kLutShift>(lut, key, [&](int i) { return st.U(sl, k, i); },
+                                              [&](int i) { return st.X(sl, i); }, [&](int i) { return st.Y(sl, i); },
+                                              [&](int i) { return st.L(sl, i); }, ex, ey, p);
             }
             if (want >= 0) atomicMin(claim + want, t);
         }
@@ -692,7 +699,6 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
     auto key2 = [&](int i) { return st.K(s2, i); };
     const uint16_t* lut1 = st.lut(s1);
     const uint16_t* lut2 = st.lut(s2);
-    auto lower1 = [&](int v) { return lower_lut<S::kLutShift>(lut1, key1, n1, v); };
     auto lower2 = [&](int v) { return lower_lut<S::kLutShift>(lut2, key2, n2, v); };
     int32_t* pref = st.pref();        // [n0 + 1]
     int32_t* eb = st.ebuf();          // a0[n0], b0[n0], a1[n0], b1[n0]
@@ -760,13 +766,25 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
         }
     }
     int nxt = pref[i0 + 1];
+    // h0's pair offset, window bounds and coordinates, read once per run of
+    // its pairs (the loop writes only the candidate arrays)
+    int cur = -1, pbase = 0, ra0 = 0, rb0 = 0, ra1 = 0;
+    float x0 = 0.0f, y0 = 0.0f;
     for (int pi = pb; pi < pe; ++pi) {
         while (pi >= nxt) nxt = pref[++i0 + 1];
-        const int o = pi - pref[i0];
-        const int len0 = eb[n0 + i0] - eb[i0];
-        const int i2 = o < len0 ? eb[i0] + o : eb[2 * n0 + i0] + (o - len0);
+        if (i0 != cur) {
+            cur = i0;
+            pbase = pref[i0];
+            ra0 = eb[i0];
+            rb0 = eb[n0 + i0];
+            ra1 = eb[2 * n0 + i0];
+            x0 = st.X(s0, i0);
+            y0 = st.Y(s0, i0);
+        }
+        const int o = pi - pbase;
+        const int len0 = rb0 - ra0;
+        const int i2 = o < len0 ? ra0 + o : ra1 + (o - len0);
         if (st.U(s2, k + 2, i2)) continue;
-        const float x0 = st.X(s0, i0), y0 = st.Y(s0, i0);
         const float tx = (st.X(s2, i2) - x0) / dz2;
         const float ty = (st.Y(s2, i2) - y0) / dz2;
         if (!(fabsf(tx) <= p.t_max && fabsf(ty) <= p.t_max)) continue;
@@ -809,7 +827,8 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
             // the disc of radius R_mid around the predicted middle point
             int lo1[2], hi1[2];
             const int nr1 = point_window(ex, ey, p.r_mid, lo1, hi1);
-            visit(lower1, key1, n1, nr1, lo1, hi1, [&](int i1) { try_mid(i1, st.X(s1, i1), st.Y(s1, i1)); });
+            visit_lut<S::kLutShift>(lut1, key1, nr1, lo1, hi1,
+                                    [&](int i1) { try_mid(i1, st.X(s1, i1), st.Y(s1, i1)); });
         }
     }
     __syncthreads();
@@ -1067,8 +1086,8 @@ __device__ bool create_tracks(S& st, const FindArgs& a, int k) {
             auto yf = [&](int i) { return st.Y(sl, i); };
             auto idf = [&](int i) { return st.L(sl, i); };
             auto search = [&](float ex, float ey) {
-                return best_hit([&](int v) { return lower_lut<S::kLutShift>(lut, key, nj, v); }, key,
-                                [&](int i) { return st.U(sl, j, i); }, xf, yf, idf, nj, ex, ey, a.p);
+                return best_hit<S::kLutShift>(lut, key, [&](int i) { return st.U(sl, j, i); }, xf, yf, idf, ex, ey,
+                                              a.p);
             };
             open = complete_plane<kG, kT>(st, a, j, t0, t0 + nw, nj, st.claimT(0), search,
                                           [&](int i) { st.set_U(sl, j, i); }, xf, yf, idf, sc.wg[sl]);
