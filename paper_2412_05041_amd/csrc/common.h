@@ -93,8 +93,9 @@ struct Work {
     int32_t* large;       // events that did not fit the first LDS tile
     int32_t* large2;      // events that did not fit the second LDS tile either
     int32_t* seg_m;       // clusters per (event, plane) segment
+    int32_t* seg_big;     // segments the one-wave clustering left to whole workgroups
     int32_t* counters;    // [1] finder events, [2] #large, [3] large-path tickets, [4] second-tile
-                          // tickets, [5] #large2, others spare
+                          // tickets, [5] #large2, [7] #seg_big, others spare
     // large-event path, per cluster (global cluster index)
     int32_t* g_claim;
     uint64_t* g_slota;

@@ -1,10 +1,12 @@
 // k_cluster.hip -- pixel clustering and azimuth-sorted hit staging.
 //
-// Three launches, one wave64 workgroup per (event, plane) segment in the first
-// and the last: (1) clustering with segment-local numbering, centroids parked
-// in the per-pixel scratch; (2) exclusive scan of the per-segment cluster
-// counts into the cluster offsets; (3) global numbering, centroid output and,
-// for the fused pipeline, the azimuth-sorted staging of each segment.
+// Four launches: (1) clustering with segment-local numbering, centroids
+// parked in the per-pixel scratch, one wave64 workgroup per (event, plane)
+// segment of at most 512 pixels; (2) the same for the larger segments, one
+// 256-thread workgroup each; (3) exclusive scan of the per-segment cluster
+// counts into the cluster offsets; (4) global numbering, centroid output and,
+// for the fused pipeline, the azimuth-sorted staging of each segment, one
+// wave per segment.
 //
 // Clustering = 8-connected components of the fired pixels.  Each pixel unites
 // with its neighbours of smaller id (same row: id-1; previous row: the three
@@ -19,9 +21,21 @@ namespace velo {
 
 namespace {
 
-constexpr int kCap = 1024;           // pixels of a segment handled in LDS
-constexpr int kStageCap = 512;       // clusters of a segment staged from registers and LDS
-static_assert(kCap < (1 << 11) && (int64_t)kCap * (kSide - 1) < (1 << 21), "a segment's packed sums fit their fields");
+constexpr int kCap = 512;                          // pixels of a segment one wave clusters in LDS
+constexpr int kSegsPerGroup = 4;                   // waves of a workgroup that clusters one large segment
+constexpr int kGroupThreads = kSegsPerGroup * kWave;
+constexpr int kGroupCap = kSegsPerGroup * kCap;    // pixels of a segment such a workgroup clusters in LDS
+constexpr int kFinalCap = 1024;                    // pixels of a segment the numbering pass keeps in registers
+constexpr int kStageCap = 512;                     // clusters of a segment staged from registers and LDS
+
+// Packed per-cluster sums of a segment clustered in LDS, one 64-bit word:
+// [sum of columns:26 | pixel count:12 | sum of rows:26].
+constexpr int kSumBits = 26, kCntBits = 12;
+static_assert(kGroupCap < (1 << kCntBits) && (int64_t)kGroupCap * (kSide - 1) < (1ll << kSumBits),
+              "a segment's packed sums fit their fields");
+__device__ __forceinline__ unsigned long long pack_pixel(uint32_t c, uint32_t r) {
+    return ((unsigned long long)c << (kSumBits + kCntBits)) | (1ull << kSumBits) | (unsigned long long)r;
+}
 constexpr int kSmallBuckets = 256;   // staging buckets for segments in LDS
 
 template <typename P>
@@ -81,6 +95,50 @@ __device__ __forceinline__ void unite_neighbours(const Id* ids, P* par, int i) {
 }
 
 
+// Synchronisation and prefix sums of a group of G threads that clusters one
+// segment: one wave (lockstep lanes; a fence orders the accesses, no barrier)
+// or the whole workgroup.  t: thread index in the group; wsum: per-wave
+// totals in LDS (whole-workgroup groups only).
+template <int G>
+struct Group {
+    int t;
+    int* wsum;
+    __device__ void sync() const {
+        if constexpr (G == kWave) wave_sync(); else __syncthreads();
+    }
+    __device__ bool any(int v) const {
+        if constexpr (G == kWave) {
+            wave_sync();
+            return __ballot(v) != 0ull;
+        } else {
+            return __syncthreads_or(v) != 0;
+        }
+    }
+    // exclusive prefix sum of v in thread order, and the total (uniform call)
+    __device__ int excl_scan(int v, int* total) const {
+        int tot;
+        const int ex = wave_excl_scan(v, &tot);
+        if constexpr (G == kWave) {
+            *total = tot;
+            return ex;
+        } else {
+            const int wv = t / kWave;
+            if (t % kWave == 0) wsum[wv] = tot;
+            __syncthreads();
+            int base = 0, all = 0;
+#pragma unroll
+            for (int q = 0; q < G / kWave; ++q) {
+                const int sq = wsum[q];
+                base += q < wv ? sq : 0;
+                all += sq;
+            }
+            __syncthreads();
+            *total = all;
+            return base + ex;
+        }
+    }
+};
+
 // Azimuth-sorted staging of the m clusters of one segment, by (key, index).
 // kbuf/tbuf: m-element scratch; hist: nb counters (LDS).  Staged entry g =
 // gbase + rank holds x, y, key and the global cluster index gbase + j.
@@ -132,54 +190,55 @@ __device__ void stage_segment(const float* cx, const float* cy, int m, int64_t g
     }
 }
 
-// Clustering of one segment with segment-local numbering, for segments above
-// kCap pixels: parent and rank arrays and the sums in the per-pixel global
-// scratch.  Writes pix_clu = local rank, seg_m = cluster count and, at
-// pixel-indexed scratch positions p0 + j, the centroid x, y and pixel count of
-// cluster j.  refuse: the scratch cannot hold the segment (overflow flag).
-template <typename Id, typename P, typename R>
+// Clustering of one segment with segment-local numbering by a group of G
+// threads, for segments above the LDS capacity: parent and rank arrays and
+// the sums in the per-pixel global scratch.  Writes pix_clu = local rank,
+// seg_m = cluster count and, at pixel-indexed scratch positions p0 + j, the
+// centroid x, y and pixel count of cluster j.  refuse: the scratch cannot
+// hold the segment (overflow flag).
+template <int G, typename Id, typename P, typename R>
 __device__ void cluster_global(const ClusterArgs& a, int seg, int p0, int n, const Id* ids, P* par, R* rnk,
-                               int refuse) {
-    const int lane = threadIdx.x;
+                               int refuse, const Group<G>& g) {
+    static_assert(G == kGroupThreads, "the global-memory path runs on the whole workgroup (its phases meet at barriers)");
+    const int t = g.t;
     const Work& w = a.w;
     const int e = seg / kPlanes;
     int bad = refuse;
     if (a.validate && !refuse) {
-        for (int i = lane; i < n; i += kWave) {
+        for (int i = t; i < n; i += G) {
             const uint32_t id = ids[i];
             if (!valid_pixel(id) || (i > 0 && ids[i - 1] >= id)) bad = 1;
         }
     }
-    bad = __syncthreads_or(bad);
-    if (bad) {
-        for (int i = lane; i < n; i += kWave) a.pix_clu[p0 + i] = -1;
-        if (lane == 0) {
+    if (g.any(bad)) {
+        for (int i = t; i < n; i += G) a.pix_clu[p0 + i] = -1;
+        if (t == 0) {
             w.seg_m[seg] = 0;
             set_event_flag(a.status, e, refuse ? EV_OVERFLOW : EV_BAD_INPUT, refuse ? 1 : 2);
         }
         return;
     }
-    for (int i = lane; i < n; i += kWave) par[i] = i;
+    for (int i = t; i < n; i += G) par[i] = i;
     __syncthreads();
-    for (int i = lane; i < n; i += kWave) unite_neighbours(ids, par, i);
+    for (int i = t; i < n; i += G) unite_neighbours(ids, par, i);
     __syncthreads();
-    for (int i = lane; i < n; i += kWave) rnk[i] = find_root(par, i);
+    for (int i = t; i < n; i += G) rnk[i] = find_root(par, i);
     __syncthreads();
     // number the roots in index order; par[root] := its rank
     int m = 0;
-    for (int c0 = 0; c0 < n; c0 += kWave) {
-        const int i = c0 + lane;
+    for (int c0 = 0; c0 < n; c0 += G) {
+        const int i = c0 + t;
         const int isroot = (i < n && rnk[i] == i) ? 1 : 0;
         int tot;
-        const int ex = wave_excl_scan(isroot, &tot);
+        const int ex = g.excl_scan(isroot, &tot);
         if (isroot) par[i] = m + ex;
         m += tot;
     }
     __syncthreads();
-    for (int i = lane; i < n; i += kWave) rnk[i] = par[rnk[i]];
-    for (int j = lane; j < m; j += kWave) { w.g_sc[p0 + j] = 0; w.g_sr[p0 + j] = 0; w.g_cnt[p0 + j] = 0; }
+    for (int i = t; i < n; i += G) rnk[i] = par[rnk[i]];
+    for (int j = t; j < m; j += G) { w.g_sc[p0 + j] = 0; w.g_sr[p0 + j] = 0; w.g_cnt[p0 + j] = 0; }
     __syncthreads();
-    for (int i = lane; i < n; i += kWave) {
+    for (int i = t; i < n; i += G) {
         const int rk = rnk[i];
         a.pix_clu[p0 + i] = rk;
         const uint32_t id = ids[i];
@@ -188,7 +247,7 @@ __device__ void cluster_global(const ClusterArgs& a, int seg, int p0, int n, con
         atomicAdd(w.g_cnt + p0 + rk, 1u);
     }
     __syncthreads();
-    for (int j = lane; j < m; j += kWave) {
+    for (int j = t; j < m; j += G) {
         const uint32_t sc = w.g_sc[p0 + j], sr = w.g_sr[p0 + j], cnt = w.g_cnt[p0 + j];
         const float fn = (float)cnt;
         // centroid parked in the scratch (same slots as the sums: read before write)
@@ -196,32 +255,36 @@ __device__ void cluster_global(const ClusterArgs& a, int seg, int p0, int n, con
         w.g_sr[p0 + j] = __float_as_uint(((float)sr / fn - 726.5f) * 0.055f);
         w.g_cnt[p0 + j] = cnt;
     }
-    if (lane == 0) w.seg_m[seg] = m;
+    if (t == 0) w.seg_m[seg] = m;
 }
 
-// Clustering of a segment of at most kCap pixels, one wave.  Per-pixel state
-// (id, root, rank; pixel i = lane + 64 r) stays in registers; only the ids and
-// the union-find parents live in LDS (kCap words each), and once the ranks are
-// known that space holds the packed per-cluster sums.  Same outputs as
-// cluster_global.
-__device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsigned long long* s_buf) {
-    constexpr int R = kCap / kWave;
+// Clustering of a segment in LDS by a group of G threads: one wave (at most
+// kCap pixels) or the whole workgroup (at most kGroupCap).  Per-pixel state
+// (id, root, rank; pixel i = t + G r) stays in registers; only the ids and the
+// union-find parents live in LDS (one word each per pixel of the capacity),
+// and once the ranks are known that space holds the packed per-cluster sums.
+// Same outputs as cluster_global.
+template <int G>
+__device__ void cluster_lds(const ClusterArgs& a, int seg, int p0, int n, unsigned long long* s_buf,
+                            const Group<G>& g) {
+    constexpr int kC = G == kWave ? kCap : kGroupCap;
+    constexpr int R = kC / G;
     uint32_t* s_id = reinterpret_cast<uint32_t*>(s_buf);
-    int32_t* s_par = reinterpret_cast<int32_t*>(s_id + kCap);
-    const int lane = threadIdx.x;
+    int32_t* s_par = reinterpret_cast<int32_t*>(s_id + kC);
+    const int t = g.t;
     const Work& w = a.w;
     if (n == 0) {
-        if (lane == 0) w.seg_m[seg] = 0;
+        if (t == 0) w.seg_m[seg] = 0;
         return;
     }
     // All R loads are issued before the first is used (addresses clamped into
-    // the segment), so the wave waits for the ids once, not once per row.
+    // the segment), so the group waits for the ids once, not once per row.
     uint32_t id[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) id[r] = a.pix_id[p0 + min(lane + r * kWave, n - 1)];
+    for (int r = 0; r < R; ++r) id[r] = a.pix_id[p0 + min(t + r * G, n - 1)];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane + r * kWave;
+        const int i = t + r * G;
         if (i < n) {
             s_id[i] = id[r];
             s_par[i] = i;
@@ -229,18 +292,18 @@ __device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsi
             id[r] = 0u;
         }
     }
-    __syncthreads();
+    g.sync();
     int bad = 0;
     if (a.validate) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int i = lane + r * kWave;
+            const int i = t + r * G;
             if (i < n && (!valid_pixel(id[r]) || (i > 0 && s_id[i - 1] >= id[r]))) bad = 1;
         }
     }
-    if (__syncthreads_or(bad)) {
-        for (int i = lane; i < n; i += kWave) a.pix_clu[p0 + i] = -1;
-        if (lane == 0) {
+    if (g.any(bad)) {
+        for (int i = t; i < n; i += G) a.pix_clu[p0 + i] = -1;
+        if (t == 0) {
             w.seg_m[seg] = 0;
             set_event_flag(a.status, seg / kPlanes, EV_BAD_INPUT, 2);
         }
@@ -248,62 +311,65 @@ __device__ void cluster_small(const ClusterArgs& a, int seg, int p0, int n, unsi
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane + r * kWave;
+        const int i = t + r * G;
         if (i < n) unite_neighbours(s_id, s_par, i);
     }
-    __syncthreads();
+    g.sync();
     int root[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane + r * kWave;
+        const int i = t + r * G;
         root[r] = i < n ? find_root(s_par, i) : -1;
     }
-    __syncthreads();
+    g.sync();
     // number the roots in index order; par[root] := its rank
     int m = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane + r * kWave;
+        const int i = t + r * G;
         const int isroot = root[r] == i ? 1 : 0;
         int tot;
-        const int ex = wave_excl_scan(isroot, &tot);
+        const int ex = g.excl_scan(isroot, &tot);
         if (isroot) s_par[i] = m + ex;
         m += tot;
     }
-    __syncthreads();
+    g.sync();
     int rank[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rank[r] = root[r] >= 0 ? s_par[root[r]] : 0;
-    __syncthreads();
+    g.sync();
     // ids and parents are dead: the same words hold the packed sums
-    // [sum_c:32 | count:11 | sum_r:21]; n <= kCap = 1024 keeps the fields apart
-    // (count <= 1024 < 2^11, sum_r <= 1024 * 1453 < 2^21)
     unsigned long long* s_sum = s_buf;
-    for (int j = lane; j < m; j += kWave) s_sum[j] = 0;
-    __syncthreads();
+    for (int j = t; j < m; j += G) s_sum[j] = 0;
+    g.sync();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = lane + r * kWave;
+        const int i = t + r * G;
         if (i < n) {
             a.pix_clu[p0 + i] = rank[r];
-            const uint32_t c = id[r] % kSide, rr = id[r] / kSide;
-            atomicAdd(s_sum + rank[r], ((unsigned long long)c << 32) | (1ull << 21) | (unsigned long long)rr);
+            atomicAdd(s_sum + rank[r], pack_pixel(id[r] % kSide, id[r] / kSide));
         }
     }
-    __syncthreads();
-    for (int j = lane; j < m; j += kWave) {
+    g.sync();
+    for (int j = t; j < m; j += G) {
         const unsigned long long v = s_sum[j];
-        const uint32_t sc = (uint32_t)(v >> 32);
-        const uint32_t cnt = (uint32_t)((v >> 21) & 0x7ffu);
-        const uint32_t sr = (uint32_t)(v & 0x1fffffu);
+        const uint32_t sc = (uint32_t)(v >> (kSumBits + kCntBits));
+        const uint32_t cnt = (uint32_t)((v >> kSumBits) & ((1u << kCntBits) - 1u));
+        const uint32_t sr = (uint32_t)(v & ((1ull << kSumBits) - 1ull));
         const float fn = (float)cnt;
         w.g_sc[p0 + j] = __float_as_uint(((float)sc / fn - 726.5f) * 0.055f);
         w.g_sr[p0 + j] = __float_as_uint(((float)sr / fn - 726.5f) * 0.055f);
         w.g_cnt[p0 + j] = cnt;
     }
-    if (lane == 0) w.seg_m[seg] = m;
+    if (t == 0) w.seg_m[seg] = m;
 }
 
+// Counter of the segments k_cluster leaves to k_cluster_big (zeroed with the
+// other counters before every clustering).
+constexpr int kBigSegCounter = 7;
+
+// One wave per segment of at most kCap pixels; a larger segment (or one the
+// scratch refuses) is appended to the list k_cluster_big works through.
 __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
     __shared__ unsigned long long s_buf[kCap];
     const int seg = blockIdx.x;
@@ -314,9 +380,33 @@ __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
     // the per-pixel scratch covers pixel positions below its capacity
     const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
     if (n <= kCap && !refuse) {
-        cluster_small(a, seg, p0, n, s_buf);
-    } else {
-        cluster_global(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, refuse);
+        cluster_lds<kWave>(a, seg, p0, n, s_buf, Group<kWave>{(int)threadIdx.x, nullptr});
+    } else if (threadIdx.x == 0) {
+        w.seg_big[atomicAdd(w.counters + kBigSegCounter, 1)] = seg;
+    }
+}
+
+// The segments k_cluster left over, one 256-thread workgroup each (a grid
+// smaller than the list takes several in turn): in LDS up to kGroupCap
+// pixels, else in global memory.
+constexpr int kBigGrid = 1024;
+__global__ __launch_bounds__(kGroupThreads) void k_cluster_big(ClusterArgs a) {
+    __shared__ unsigned long long s_buf[kGroupCap];
+    __shared__ int s_wsum[kSegsPerGroup];
+    const Work& w = a.w;
+    const int nb = w.counters[kBigSegCounter];
+    const Group<kGroupThreads> grp{(int)threadIdx.x, s_wsum};
+    for (int q = blockIdx.x; q < nb; q += gridDim.x) {
+        const int seg = w.seg_big[q];
+        const int p0 = a.pix_off[seg];
+        const int n = a.pix_off[seg + 1] - p0;
+        const int refuse = (int64_t)p0 + n > w.cap_scratch ? 1 : 0;
+        if (n <= kGroupCap && !refuse) {
+            cluster_lds<kGroupThreads>(a, seg, p0, n, s_buf, grp);
+        } else {
+            cluster_global<kGroupThreads>(a, seg, p0, n, a.pix_id + p0, w.g_par + p0, w.g_tmp + p0, refuse, grp);
+        }
+        __syncthreads();  // the LDS is free for the next segment
     }
 }
 
@@ -456,13 +546,13 @@ __device__ void stage_regs(const float (&cx)[kStageCap / kWave], const float (&c
     }
 }
 
-// Global numbering, centroid output and staging of a segment of at most kCap
-// pixels and kStageCap clusters, one wave.  Every global load (the segment's
+// Global numbering, centroid output and staging of a segment of at most
+// kFinalCap pixels and kStageCap clusters, one wave.  Every global load (the segment's
 // local labels and parked centroids) is issued at once into registers, with
 // addresses clamped into the segment; the staging then works from registers
 // and LDS.  Same outputs as the general loops of k_cluster_final.
 __device__ void final_small(const ClusterArgs& a, int seg, int p0, int n, int64_t cb, int m, StageLds& lds) {
-    constexpr int R = kCap / kWave;
+    constexpr int R = kFinalCap / kWave;
     constexpr int RM = kStageCap / kWave;
     const int lane = threadIdx.x;
     const Work& w = a.w;
@@ -520,7 +610,7 @@ __global__ __launch_bounds__(kWave) void k_cluster_final(ClusterArgs a) {
     // refused in the first pass (m is always >= 0: the test only makes the
     // branch need both offset loads, so that they are in flight together)
     if (((int64_t)p0 + n > w.cap_scratch) | (m < 0)) return;
-    if (n <= kCap && m <= kStageCap) {
+    if (n <= kFinalCap && m <= kStageCap) {
         final_small(a, seg, p0, n, cb, m, s_lds);
         return;
     }
@@ -575,10 +665,14 @@ __global__ __launch_bounds__(kWave) void k_stage(StageArgs a) {
 
 }  // namespace
 
+// The counters must be zero (launch_reset), as before every clustering.
 hipError_t launch_cluster(const ClusterArgs& a, hipStream_t s) {
     if (a.n_seg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cluster, dim3(a.n_seg), dim3(kWave), 0, s, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cluster_big, dim3(a.n_seg < kBigGrid ? a.n_seg : kBigGrid), dim3(kGroupThreads), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_seg, dim3(1), dim3(1024), 0, s, a);
     e = hipGetLastError();

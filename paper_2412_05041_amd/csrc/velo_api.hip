@@ -150,6 +150,7 @@ size_t layout(Work& w, char* base, int32_t E, int64_t P, int64_t C, int n_cu, in
     w.large = carve<int32_t>(cur, E);
     w.large2 = carve<int32_t>(cur, E);
     w.seg_m = carve<int32_t>(cur, (int64_t)E * kPlanes);
+    w.seg_big = carve<int32_t>(cur, (int64_t)E * kPlanes);
     w.counters = carve<int32_t>(cur, 8);
     w.g_claim = carve<int32_t>(cur, C);
     w.g_slota = carve<uint64_t>(cur, C);
