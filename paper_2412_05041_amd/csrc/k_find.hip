@@ -172,6 +172,8 @@ struct LdsStore {
     // enumeration scratch (seeding slots are free before the claiming rounds)
     __device__ int32_t* pref() { return reinterpret_cast<int32_t*>(&t->slotb[0][0]); }
     __device__ int32_t* ebuf() { return reinterpret_cast<int32_t*>(&t->slota[0][0]); }
+    // h0 of each thread's first seed pair (after the window bounds ebuf holds)
+    __device__ int32_t* first_h0() { return ebuf() + 4 * kP; }
     // seed-filter broadcast scratch: 2 x 32 floats for each of a round's (at
     // most 16) candidate groups, in the seeding slots (still free then)
     __device__ float* bcast() { return reinterpret_cast<float*>(&t->slota[0][0]); }
@@ -346,18 +348,32 @@ __device__ __forceinline__ int lower_lut(const uint16_t* lut, KF key, int n, int
 // Visits every position of a key-sorted plane whose key lies in the ranges
 // lo[r] .. hi[r], through its bucket index lut (lut[b] = first position whose
 // key bucket is >= b): every position of the buckets a range touches, with
-// the key test inside.  The ends of a range are not searched for, so a visit
-// starts after one index read instead of a chain of key reads.
-template <int kShift, class KF, class F>
-__device__ __forceinline__ void visit_lut(const uint16_t* lut, KF key, int nr, const int* lo, const int* hi, F f) {
+// the key test inside, so the ends of a range are not searched for.  A
+// position's data (load(i)) is read together with its key, two positions at
+// a time, and f(i, data) sees the ones that pass: a visit waits for one round
+// of reads per two positions instead of a chain of key reads and data reads.
+template <int kShift, class KF, class LF, class F>
+__device__ __forceinline__ void visit_lut(const uint16_t* lut, KF key, LF load, int nr, const int* lo, const int* hi,
+                                          F f) {
     for (int r = 0; r < nr; ++r) {
         const int i1 = lut[(hi[r] >> kShift) + 1];
-        for (int i = lut[lo[r] >> kShift]; i < i1; ++i) {
-            const int k = key(i);
-            if (k >= lo[r] && k <= hi[r]) f(i);
+        for (int i = lut[lo[r] >> kShift]; i < i1; i += 2) {
+            const int j = min(i + 1, i1 - 1);
+            const int ka = key(i), kb = key(j);
+            const auto da = load(i);
+            const auto db = load(j);
+            if (ka >= lo[r] && ka <= hi[r]) f(i, da);
+            if (j > i && kb >= lo[r] && kb <= hi[r]) f(j, db);
         }
     }
 }
+
+// What a window search reads of a staged position besides its key.
+struct PosData {
+    float x, y;
+    int id;
+    bool used;
+};
 
 // Half-width in keys of the azimuth range subtended by a disc of radius R seen
 // at distance r (asin(R/r) plus margins), or -1 when the whole circle is needed.
@@ -375,14 +391,14 @@ __device__ __forceinline__ int best_hit(const uint16_t* lut, KF key, UF used, XF
     const int nr = point_window(ex, ey, p.r_ext, lo, hi);
     float bq = 0.0f;
     int bid = kIntMax, want = -1;
-    visit_lut<kShift>(lut, key, nr, lo, hi, [&](int i) {
-        if (used(i)) return;
-        const float dx = xf(i) - ex;
-        const float dy = yf(i) - ey;
+    auto load = [&](int i) { return PosData{xf(i), yf(i), idf(i), used(i)}; };
+    visit_lut<kShift>(lut, key, load, nr, lo, hi, [&](int i, const PosData& d) {
+        if (d.used) return;
+        const float dx = d.x - ex;
+        const float dy = d.y - ey;
         const float q = dx * dx + dy * dy;
         if (!(q <= p.e_max)) return;
-        const int id = idf(i);
-        if (want < 0 || q < bq || (q == bq && id < bid)) { want = i; bq = q; bid = id; }
+        if (want < 0 || q < bq || (q == bq && d.id < bid)) { want = i; bq = q; bid = d.id; }
     });
     return want;
 }
@@ -745,6 +761,15 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
         }
         if ((int)threadIdx.x < n0) pref[threadIdx.x] = base + ex;
         if (threadIdx.x == 0) pref[n0] = total;
+        if constexpr (!S::kLarge) {
+            // (C) below gives thread t the pairs from t * per on; the h0 whose
+            // pairs [base + ex, base + ex + cnt) hold that pair tells t so
+            static_assert(S::kLarge || 2 * S::kPlaneCap >= kT, "first_h0 fits the seeding slots");
+            const int per = (total + kT - 1) / kT;
+            int32_t* first = st.first_h0();
+            for (int t = (base + ex + per - 1) / max(per, 1); cnt > 0 && t * per < base + ex + cnt; ++t)
+                first[t] = threadIdx.x;
+        }
         __syncthreads();
     } else {
         for (int i0 = threadIdx.x; i0 < n0; i0 += kT) pref[i0] = window(i0);
@@ -753,16 +778,25 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
         block_excl_scan<kT>(pref, n0, sc);
     }
     const int np = pref[n0];
-    // (C) each thread takes a contiguous run of pairs: one search for its
-    // first h0, then a forward walk
+    // (C) each thread takes a contiguous run of pairs: its first h0 (marked
+    // above, or one search), then a forward walk
     const int per = (np + kT - 1) / kT;
     const int pb = min(np, (int)threadIdx.x * per), pe = min(np, pb + per);
     int i0 = 0;
     if (pb < pe) {
-        int hi = n0;  // last i0 with pref[i0] <= pb
-        while (hi - i0 > 1) {
-            const int mid = (i0 + hi) >> 1;
-            if (pref[mid] <= pb) i0 = mid; else hi = mid;
+        bool known = false;
+        if constexpr (!S::kLarge) {
+            if (n0 <= kT) {
+                i0 = st.first_h0()[threadIdx.x];
+                known = true;
+            }
+        }
+        if (!known) {
+            int hi = n0;  // last i0 with pref[i0] <= pb
+            while (hi - i0 > 1) {
+                const int mid = (i0 + hi) >> 1;
+                if (pref[mid] <= pb) i0 = mid; else hi = mid;
+            }
         }
     }
     int nxt = pref[i0 + 1];
@@ -793,8 +827,8 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
         if (!(cr * cr <= p.d2_max * (tx * tx + ty * ty))) continue;
         const float ex = x0 + tx * dz1;
         const float ey = y0 + ty * dz1;
-        auto try_mid = [&](int i1, float x1, float y1) {
-            if (st.U(s1, k + 1, i1)) return;
+        auto try_mid = [&](int i1, float x1, float y1, bool used1) {
+            if (used1) return;
             const float dx = x1 - ex;
             const float dy = y1 - ey;
             const float q = dx * dx + dy * dy;
@@ -822,13 +856,17 @@ __device__ bool enumerate_seeds(S& st, const FindArgs& a, int k, const SeedRange
             // crowded planes: the disc of radius R_mid around the prediction
             const int64_t g1 = sc.wg[s1];
             grid_visit(st.cells(k + 1), ex, ey, p.r_mid,
-                       [&](int q1) { try_mid(a.w.g_gpos[g1 + q1], a.w.g_gx[g1 + q1], a.w.g_gy[g1 + q1]); });
+                       [&](int q1) {
+                           const int i1 = a.w.g_gpos[g1 + q1];
+                           try_mid(i1, a.w.g_gx[g1 + q1], a.w.g_gy[g1 + q1], st.U(s1, k + 1, i1));
+                       });
         } else {
             // the disc of radius R_mid around the predicted middle point
             int lo1[2], hi1[2];
             const int nr1 = point_window(ex, ey, p.r_mid, lo1, hi1);
-            visit_lut<S::kLutShift>(lut1, key1, nr1, lo1, hi1,
-                                    [&](int i1) { try_mid(i1, st.X(s1, i1), st.Y(s1, i1)); });
+            auto load1 = [&](int i1) { return PosData{st.X(s1, i1), st.Y(s1, i1), 0, st.U(s1, k + 1, i1)}; };
+            visit_lut<S::kLutShift>(lut1, key1, load1, nr1, lo1, hi1,
+                                    [&](int i1, const PosData& d) { try_mid(i1, d.x, d.y, d.used); });
         }
     }
     __syncthreads();
