@@ -22,9 +22,9 @@ namespace velo {
 namespace {
 
 constexpr int kCap = 512;                          // pixels of a segment one wave clusters in LDS
-constexpr int kSegsPerGroup = 4;                   // waves of a workgroup that clusters one large segment
-constexpr int kGroupThreads = kSegsPerGroup * kWave;
-constexpr int kGroupCap = kSegsPerGroup * kCap;    // pixels of a segment such a workgroup clusters in LDS
+constexpr int kBigWaves = 4;                       // waves of a workgroup that clusters one large segment
+constexpr int kGroupThreads = kBigWaves * kWave;
+constexpr int kGroupCap = kBigWaves * kCap;        // pixels of a segment such a workgroup clusters in LDS
 constexpr int kFinalCap = 1024;                    // pixels of a segment the numbering pass keeps in registers
 constexpr int kStageCap = 512;                     // clusters of a segment staged from registers and LDS
 
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kWave) void k_cluster(ClusterArgs a) {
 constexpr int kBigGrid = 1024;
 __global__ __launch_bounds__(kGroupThreads) void k_cluster_big(ClusterArgs a) {
     __shared__ unsigned long long s_buf[kGroupCap];
-    __shared__ int s_wsum[kSegsPerGroup];
+    __shared__ int s_wsum[kBigWaves];
     const Work& w = a.w;
     const int nb = w.counters[kBigSegCounter];
     const Group<kGroupThreads> grp{(int)threadIdx.x, s_wsum};
