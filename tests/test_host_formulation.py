@@ -137,6 +137,62 @@ def test_seed_windows_contain_every_passing_triplet():
 
 
 
+
+def point_windows(ex, ey, R):
+    """The extension and middle-hit windows as the finder bounds them (FP32,
+    vectorised): the azimuth of E from an octant reduction and the odd
+    degree-9 polynomial of Abramowitz & Stegun 4.4.49, the half-angle from
+    R / sqrt(|E|^2 - R^2) >= asin(R/|E|) widened by 0.1 %, then 1e-4 rad and
+    two keys on each side.  The hardware reciprocal square root is taken one
+    part in 2^22 low (it may round either way).  Returns (lo, hi, whole)."""
+    ex, ey, R = np.asarray(ex, f32), np.asarray(ey, f32), f32(R)
+    e2 = ex * ex + ey * ey
+    whole = ~(e2 > f32(4.0) * R * R)
+    rsq = (f32(1.0) / np.sqrt(np.maximum(e2 - R * R, f32(1e-30)))).astype(f32) * f32(1.0 - 2.0 ** -22)
+    half = R * rsq * f32(1.001) + f32(1e-4)
+    ax, ay = np.abs(ex), np.abs(ey)
+    t = np.minimum(ax, ay) * (f32(1.0) / np.maximum(np.maximum(ax, ay), f32(1e-30)))
+    sq = t * t
+    phi = t * (f32(0.9998660) + sq * (f32(-0.3302995) + sq * (f32(0.1801410) + sq * (f32(-0.0851330)
+                                                                                   + sq * f32(0.0208351)))))
+    phi = np.where(ay > ax, f32(1.57079633) - phi, phi)
+    phi = np.where(ex < 0, PI - phi, phi)
+    phi = np.where(ey < 0, -phi, phi)
+    c = (phi + PI) * KEYS_PER_RAD
+    w = half * KEYS_PER_RAD
+    lo = np.floor(c - w).astype(np.int64) - 2
+    hi = np.ceil(c + w).astype(np.int64) + 2
+    return lo, hi, whole
+
+
+@pytest.mark.parametrize("cut", ["e_max", "s_max"])
+def test_point_windows_contain_every_hit_passing_the_cut(cut):
+    """Every hit within the FP32 cut of a predicted point E (extension: e_max;
+    middle hit: s_max) has its azimuth key inside the window around E."""
+    rng = np.random.default_rng(11 if cut == "e_max" else 12)
+    q_max = f32(0.25) if cut == "e_max" else f32(0.09)
+    R = math.sqrt(float(q_max)) * 1.0001 + 1e-6  # the radius the host gives the kernels
+    n = 400000
+    rE = np.concatenate([rng.uniform(2 * R, 3 * R, n // 4), rng.uniform(3 * R, 45.0, n - n // 4)])
+    aE = rng.uniform(-math.pi, math.pi, n)
+    # a quarter exactly on the axes and octant diagonals, where the reduction switches
+    aE[: n // 4] = rng.choice(np.arange(-4, 5) * (math.pi / 4), n // 4)
+    ex = (rE * np.cos(aE)).astype(f32)
+    ey = (rE * np.sin(aE)).astype(f32)
+    rr = np.where(rng.random(n) < 0.3, math.sqrt(float(q_max)), math.sqrt(float(q_max)) * np.sqrt(rng.random(n)))
+    ah = rng.uniform(0, 2 * math.pi, n)
+    hx = (ex + rr * np.cos(ah)).astype(f32)
+    hy = (ey + rr * np.sin(ah)).astype(f32)
+    dx, dy = hx - ex, hy - ey
+    passing = dx * dx + dy * dy <= q_max
+    assert passing.sum() > n // 2
+    lo, hi, whole = point_windows(ex, ey, R)
+    k = phi_key(hx, hy)
+    inside = whole | ((lo <= k) & (k <= hi)) | ((lo <= k - 65536) & (k - 65536 <= hi)) | \
+        ((lo <= k + 65536) & (k + 65536 <= hi))
+    bad = np.nonzero(passing & ~inside)[0]
+    assert bad.size == 0, (bad[:5], ex[bad[:5]], ey[bad[:5]], hx[bad[:5]], hy[bad[:5]])
+
 def grid_cell1(v):
     """Cell of a coordinate as the kernels compute it (FP32): 0.5 mm cells over [-40, 40] mm."""
     c = np.floor((np.asarray(v, f32) + f32(40.0)) * f32(2.0))
